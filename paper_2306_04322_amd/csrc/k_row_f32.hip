@@ -1,0 +1,3 @@
+// Row-pass instantiations, single precision.
+#define PF_T float
+#include "k_row.inc"

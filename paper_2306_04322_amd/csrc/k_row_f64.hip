@@ -1,0 +1,3 @@
+// Row-pass instantiations, double precision.
+#define PF_T double
+#include "k_row.inc"

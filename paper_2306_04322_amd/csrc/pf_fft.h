@@ -1,0 +1,191 @@
+// Device-side FFT building blocks for gfx950.
+//
+// A length-N complex transform is executed by a "team" of N/E lanes, each
+// lane holding E elements in registers.  Lane t of a team always holds
+// element t + TEAM*m in register m, both on entry (time order) and on exit
+// (frequency order), so the first pass reads straight from registers loaded
+// with coalesced global loads and the last pass leaves the result in
+// registers ready for coalesced stores.
+//
+// The transform is a mixed-radix Stockham autosort FFT: for a pass of radix
+// R after NS points have been combined, butterfly j (0 <= j < N/R) reads
+// x[j + r N/R], multiplies input r by exp(-+2 pi i r k / (NS R)) with
+// k = j mod NS, applies an R-point DFT and writes y[(j - k) R + k + r NS].
+// Between passes the data goes through LDS; the last pass writes its
+// outputs back to the same registers it read (its output index equals its
+// input index), so an N = E^P transform needs P - 1 LDS exchanges.
+//
+// Twiddles come from a per-axis table W[q] = exp(-2 pi i q / Naxis) that the
+// host computes in double precision (rounded once for float); a length-N
+// transform on an axis of length Naxis reads W[q * (Naxis / N)].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pf {
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+template <typename T> using c2 = typename vec2<T>::type;
+
+template <typename T>
+__device__ __forceinline__ c2<T> mk(T x, T y) {
+  c2<T> r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ c2<T> add(c2<T> a, c2<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ c2<T> sub(c2<T> a, c2<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ c2<T> cmul(c2<T> a, c2<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ c2<T> cmulc(c2<T> a, c2<T> b) {
+  return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__device__ __forceinline__ c2<T> conj(c2<T> a) { return mk<T>(a.x, -a.y); }
+template <typename T>
+__device__ __forceinline__ c2<T> scale(c2<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// Multiply by exp(-2 pi i K / R) (forward) or exp(+2 pi i K / R) (inverse)
+// for R <= 16, 0 <= K < R/2.  Exact sixteenth roots of unity: cos(pi/8),
+// sin(pi/8) and sqrt(1/2) to 21 digits.
+template <int R, int K, bool INV, typename T>
+__device__ __forceinline__ c2<T> rot(c2<T> a) {
+  constexpr int k16 = K * (16 / R);
+  constexpr double C1 = 0.92387953251128675612818;  // cos(pi/8)
+  constexpr double S1 = 0.38268343236508977172846;  // sin(pi/8)
+  constexpr double R2 = 0.70710678118654752440084;  // sqrt(1/2)
+  if constexpr (k16 == 0) {
+    return a;
+  } else if constexpr (k16 == 4) {
+    // forward: * (-i); inverse: * (+i)
+    return INV ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+  } else {
+    constexpr double cs = (k16 == 1) ? C1 : (k16 == 2) ? R2 : (k16 == 3) ? S1
+                        : (k16 == 5) ? -S1 : (k16 == 6) ? -R2 : -C1;
+    constexpr double sn = (k16 == 1) ? S1 : (k16 == 2) ? R2 : (k16 == 3) ? C1
+                        : (k16 == 5) ? C1 : (k16 == 6) ? R2 : S1;
+    // w = cs - i sn (forward) or cs + i sn (inverse)
+    const T c = T(cs);
+    const T s = INV ? T(sn) : T(-sn);
+    return mk<T>(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+// R-point DFT in registers, natural order in and out (radix-2 decimation in
+// time, unrolled at compile time).
+template <typename T, int R, bool INV>
+struct Dft;
+
+template <typename T, bool INV>
+struct Dft<T, 1, INV> {
+  __device__ __forceinline__ static void run(c2<T>*) {}
+};
+
+template <int K, int R, bool INV, typename T>
+struct Combine {
+  __device__ __forceinline__ static void run(c2<T>* x, const c2<T>* e, const c2<T>* o) {
+    Combine<K - 1, R, INV, T>::run(x, e, o);
+    const c2<T> t = rot<R, K - 1, INV, T>(o[K - 1]);
+    x[K - 1] = add<T>(e[K - 1], t);
+    x[K - 1 + R / 2] = sub<T>(e[K - 1], t);
+  }
+};
+template <int R, bool INV, typename T>
+struct Combine<0, R, INV, T> {
+  __device__ __forceinline__ static void run(c2<T>*, const c2<T>*, const c2<T>*) {}
+};
+
+template <typename T, int R, bool INV>
+struct Dft {
+  __device__ __forceinline__ static void run(c2<T>* x) {
+    c2<T> e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      e[i] = x[2 * i];
+      o[i] = x[2 * i + 1];
+    }
+    Dft<T, R / 2, INV>::run(e);
+    Dft<T, R / 2, INV>::run(o);
+    Combine<R / 2, R, INV, T>::run(x, e, o);
+  }
+};
+
+// Radix of the first pass: the remainder when log2(N) is not a multiple of
+// log2(E); every later pass has radix E.
+template <int N, int E>
+constexpr int first_radix() {
+  return (ilog2(N) % ilog2(E)) ? (1 << (ilog2(N) % ilog2(E))) : E;
+}
+
+// One Stockham pass.  `lds` points at element 0 of this team's exchange
+// area; element i lives at lds[i * LS].
+template <typename T, int N, int E, int R, int NS, bool INV, bool LAST, int LS>
+__device__ __forceinline__ void stockham_pass(c2<T>* v, int t, c2<T>* lds,
+                                              const c2<T>* __restrict__ tw, int tws) {
+  constexpr int TEAM = N / E;
+  constexpr int BPL = E / R;  // butterflies per lane
+#pragma unroll
+  for (int b = 0; b < BPL; ++b) {
+    const int j = t + TEAM * b;
+    const int k = j & (NS - 1);
+    c2<T> x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = v[b + r * BPL];
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        c2<T> w = tw[(r * k * (N / (NS * R))) * tws];
+        x[r] = INV ? cmulc<T>(x[r], w) : cmul<T>(x[r], w);
+      }
+    }
+    Dft<T, R, INV>::run(x);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + r * BPL] = x[r];
+    } else {
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[(base + r * NS) * LS] = x[r];
+    }
+  }
+}
+
+template <typename T, int N, int E, bool INV, int NS, int LS>
+struct FftPasses {
+  static constexpr int R = (NS == 1) ? first_radix<N, E>() : E;
+  static constexpr bool LAST = (NS * R == N);
+  __device__ __forceinline__ static void run(c2<T>* v, int t, c2<T>* lds,
+                                             const c2<T>* __restrict__ tw, int tws) {
+    stockham_pass<T, N, E, R, NS, INV, LAST, LS>(v, t, lds, tw, tws);
+    if constexpr (!LAST) {
+      constexpr int TEAM = N / E;
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = lds[(t + TEAM * m) * LS];
+      __syncthreads();
+      FftPasses<T, N, E, INV, NS * R, LS>::run(v, t, lds, tw, tws);
+    }
+  }
+};
+
+// Length-N complex FFT by a team; unnormalised in both directions.
+// Every lane of the work-group must call this (it contains barriers).
+template <typename T, int N, int E, bool INV, int LS>
+__device__ __forceinline__ void team_fft(c2<T>* v, int t, c2<T>* lds,
+                                         const c2<T>* __restrict__ tw, int tws) {
+  static_assert(N >= E && E >= 2 && (N % E) == 0, "bad FFT team shape");
+  FftPasses<T, N, E, INV, 1, LS>::run(v, t, lds, tw, tws);
+}
+
+}  // namespace pf

@@ -1,0 +1,405 @@
+// Kernel templates of the FS step.
+//
+// Data layout in HBM (complex values interleaved re/im):
+//   real fields   [F][Nz][Ny][Nx]            element type T
+//   x-spectra     [G][Nz][Ny][Sx]            c2<T>, row r holds the real-to-
+//                                            complex transform along x of
+//                                            row r: Nx/2 + 1 values, padded
+//                                            to the 128-byte row stride Sx
+// A "row" is one (z, y) line along x; rows = Ny * Nz.
+//
+// Row pass (xpass_kernel): one team of lanes per row transforms along the
+// contiguous x axis.  Depending on `flags` it loads real rows or inverse-
+// transforms x-spectra back to real rows (C2R), optionally stores the real
+// rows, evaluates the free-energy derivative and forward-transforms (R2C)
+// the right-hand-side combinations, and accumulates double-precision sums.
+//
+// Column pass (col_kernel): transforms along a strided axis (y, or z in
+// 3D) for a tile of C consecutive x-spectrum columns.  Lanes are laid out
+// column-fastest so every global access of a wavefront covers contiguous
+// 128-byte row segments.  Modes: forward only, inverse only, the k-space
+// update of Eq. (12)-(15) between a forward and an inverse transform, the
+// adjoint multipliers, and the spectral gradient-energy sums.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pf_fe.h"
+#include "pf_fft.h"
+
+namespace pf {
+
+enum {
+  X_LOAD_REAL = 1,   // read real rows (else C2R of s_in)
+  X_STORE_REAL = 2,  // write the real rows to u_out
+  X_FWD_DERIV = 4,   // R2C of [c, df/dc, eta_i - dt L df/deta_i] -> b_out (F+1 fields)
+  X_FWD_RAW = 8,     // R2C of the F real rows as they are -> b_out
+  X_ESUM = 16        // double sums of f(u) and c -> partials[block][2]
+};
+
+template <typename T>
+struct XArgs {
+  const T* u_in;
+  T* u_out;
+  const c2<T>* s_in;
+  c2<T>* b_out;
+  const c2<T>* twx;  // exp(-2 pi i q / Nx), q < Nx
+  double* partials;
+  long long fs_real;  // field stride of real arrays (elements)
+  long long fs_spec;  // field stride of x-spectra (complex elements)
+  int rows, Sx, F, flags;
+  FeParams<T> fe;
+  T dtL;
+};
+
+// Row pass geometry for a real length NX.
+template <typename T, int NX, int PMAX>
+struct XGeom {
+  static constexpr int NH = NX / 2;
+  static constexpr int EW = (sizeof(T) == 8 || PMAX > 4) ? 4 : 8;
+  static constexpr int E = NH < EW ? NH : EW;
+  static constexpr int TEAM = NH / E;
+  static constexpr int ROWS = TEAM >= 64 ? 1 : 64 / TEAM;
+  static constexpr int WG = ROWS * TEAM;
+  static constexpr int REGION = NH + 1;  // LDS complex values per team
+};
+
+// C2R of one row: x-spectrum src[0..NH] -> v[m] = (x[2k], x[2k+1]),
+// k = t + TEAM m, with x the unnormalised inverse over the Hermitian
+// extension (x_j = sum_k X_k exp(+2 pi i j k / NX)).
+template <typename T, int NX, int E>
+__device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src, bool active,
+                                        int t, c2<T>* my, const c2<T>* __restrict__ twx) {
+  constexpr int NH = NX / 2;
+  constexpr int TEAM = NH / E;
+  c2<T> X[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) X[m] = active ? src[t + TEAM * m] : mk<T>(T(0), T(0));
+#pragma unroll
+  for (int m = 0; m < E; ++m) my[t + TEAM * m] = X[m];
+  if (t == 0) my[NH] = active ? src[NH] : mk<T>(T(0), T(0));
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = t + TEAM * m;
+    const c2<T> Y = conj<T>(my[NH - k]);
+    const c2<T> s = add<T>(X[m], Y);
+    const c2<T> d = cmulc<T>(sub<T>(X[m], Y), twx[k]);  // * exp(+2 pi i k / NX)
+    v[m] = mk<T>(s.x - d.y, s.y + d.x);                 // s + i d
+  }
+  __syncthreads();
+  team_fft<T, NH, E, true, 1>(v, t, my, twx, 2);
+}
+
+// R2C of one row held as v[m] = (x[2k], x[2k+1]); writes X[0..NH] to dst.
+template <typename T, int NX, int E>
+__device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* __restrict__ dst, bool active, int t,
+                                        c2<T>* my, const c2<T>* __restrict__ twx) {
+  constexpr int NH = NX / 2;
+  constexpr int TEAM = NH / E;
+  team_fft<T, NH, E, false, 1>(v, t, my, twx, 2);
+#pragma unroll
+  for (int m = 0; m < E; ++m) my[t + TEAM * m] = v[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = t + TEAM * m;
+    const c2<T> Z = v[m];
+    const c2<T> Zc = conj<T>(my[(NH - k) & (NH - 1)]);
+    const c2<T> s = add<T>(Z, Zc);  // 2 A_k
+    const c2<T> d = sub<T>(Z, Zc);  // 2 i B_k
+    const c2<T> B2 = mk<T>(d.y, -d.x);  // 2 B_k
+    const c2<T> WB = cmul<T>(B2, twx[k]);
+    if (active) dst[k] = mk<T>(T(0.5) * (s.x + WB.x), T(0.5) * (s.y + WB.y));
+    if (k == 0 && active) dst[NH] = mk<T>(T(0.5) * (s.x - B2.x), T(0.5) * (s.y - B2.y));
+  }
+  __syncthreads();
+}
+
+template <typename T, int NX, int PMAX>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, XGeom<T, NX, PMAX>::WG)))
+xpass_kernel(XArgs<T> a) {
+  using G = XGeom<T, NX, PMAX>;
+  constexpr int NH = G::NH, E = G::E, TEAM = G::TEAM, ROWS = G::ROWS;
+  constexpr int FB = PMAX + 1;
+  __shared__ c2<T> lds[ROWS * G::REGION];
+  __shared__ double red[2 * (G::WG / 64 + 1)];
+  const int lane = threadIdx.x;
+  const int team = lane / TEAM;
+  const int t = lane - team * TEAM;
+  const int row = blockIdx.x * ROWS + team;
+  const bool active = row < a.rows;
+  const long long rrow = active ? row : 0;
+  c2<T>* my = lds + team * G::REGION;
+  const int F = a.F;
+  const int p = F - 1;
+
+  c2<T> u[FB][E];
+  if (a.flags & X_LOAD_REAL) {
+#pragma unroll
+    for (int f = 0; f < FB; ++f)
+      if (f < F) {
+        const c2<T>* src = reinterpret_cast<const c2<T>*>(a.u_in + f * a.fs_real + rrow * NX);
+#pragma unroll
+        for (int m = 0; m < E; ++m) u[f][m] = active ? src[t + TEAM * m] : mk<T>(T(0), T(0));
+      }
+  } else {
+#pragma unroll
+    for (int f = 0; f < FB; ++f)
+      if (f < F) row_c2r<T, NX, E>(u[f], a.s_in + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+  }
+
+  if ((a.flags & X_STORE_REAL) && active) {
+#pragma unroll
+    for (int f = 0; f < FB; ++f)
+      if (f < F) {
+        c2<T>* dst = reinterpret_cast<c2<T>*>(a.u_out + f * a.fs_real + rrow * NX);
+#pragma unroll
+        for (int m = 0; m < E; ++m) dst[t + TEAM * m] = u[f][m];
+      }
+  }
+
+  if (a.flags & X_ESUM) {
+    double acc[2] = {0.0, 0.0};
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          T eta[PMAX];
+#pragma unroll
+          for (int i = 0; i < PMAX; ++i) eta[i] = (i < p) ? (h ? u[1 + i][m].y : u[1 + i][m].x) : T(0);
+          const T c = h ? u[0][m].y : u[0][m].x;
+          acc[0] += fe_density<T, PMAX>(a.fe, p, c, eta);
+          acc[1] += double(c);
+        }
+      }
+    }
+    block_sum<2>(acc, red);
+    if (threadIdx.x == 0) {
+      a.partials[2 * blockIdx.x + 0] = acc[0];
+      a.partials[2 * blockIdx.x + 1] = acc[1];
+    }
+  }
+
+  if (a.flags & X_FWD_DERIV) {
+    // outputs: 0 -> c, 1 -> df/dc, 2 + i -> eta_i - dt L df/deta_i
+    c2<T> gcv[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      T gcx, gcy;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        T eta[PMAX], ge[PMAX];
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i) {
+          eta[i] = (i < p) ? (h ? u[1 + i][m].y : u[1 + i][m].x) : T(0);
+          ge[i] = T(0);
+        }
+        const T c = h ? u[0][m].y : u[0][m].x;
+        T gc;
+        fe_grad<T, PMAX>(a.fe, p, c, eta, gc, ge);
+        if (h) gcy = gc; else gcx = gc;
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i)
+          if (i < p) {
+            const T b = eta[i] - a.dtL * ge[i];
+            if (h) u[1 + i][m].y = b; else u[1 + i][m].x = b;
+          }
+      }
+      gcv[m] = mk<T>(gcx, gcy);
+    }
+    row_r2c<T, NX, E>(u[0], a.b_out + 0 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+    row_r2c<T, NX, E>(gcv, a.b_out + 1 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+#pragma unroll
+    for (int i = 0; i < PMAX; ++i)
+      if (i < p) row_r2c<T, NX, E>(u[1 + i], a.b_out + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+  } else if (a.flags & X_FWD_RAW) {
+#pragma unroll
+    for (int f = 0; f < FB; ++f)
+      if (f < F) row_r2c<T, NX, E>(u[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass.
+
+enum { COL_FWD = 0, COL_INV = 1, COL_UPDATE = 2, COL_ADJ = 3, COL_ENERGY = 4 };
+
+template <typename T>
+struct ColArgs {
+  const c2<T>* src;
+  c2<T>* dst;
+  const c2<T>* tw;     // exp(-2 pi i q / N) for the transformed axis
+  const T* kcol;       // |xi|^2 table indexed by the column (x frequency)
+  const T* kaxis;      // |xi|^2 table of the transformed axis
+  const T* kouter;     // |xi|^2 table indexed by the outer index (3D z pass), or null
+  const double* mean_c;  // double mean of c (held k = 0 mode)
+  double* partials;
+  long long fs_src, fs_dst;  // field strides (complex elements)
+  long long ls;              // stride between consecutive transform elements
+  long long os;              // stride between outer planes
+  int ncols;                 // active columns (Nx/2 + 1)
+  int nyq;                   // Nx/2 (Hermitian weight 1 at columns 0 and nyq)
+  int F, mode;
+  T dtM, dtMkc, dtL, dtLke, invP;
+};
+
+// E elements per lane; C columns per work-group (C * 8 or 16 bytes per row
+// segment), at least one wavefront and at most 512 lanes per group (so a
+// lane may use up to 256 VGPRs), and at most 128 KiB of LDS.
+template <typename T, int N>
+struct ColGeom {
+  static constexpr int E = N <= 8 ? N : ((N <= 512 || sizeof(T) == 8) ? 8 : 16);
+  static constexpr int TEAM = N / E;
+  static constexpr int CB = sizeof(T) == 8 ? 8 : 16;  // 128-byte row segments
+  static constexpr int LDSMAX = 128 * 1024;
+  static constexpr int C0 = (CB * TEAM < 64) ? 64 / TEAM : CB;
+  static constexpr int C1 = (C0 * TEAM > 512) ? 512 / TEAM : C0;
+  static constexpr int C = (C1 * N * (int)sizeof(c2<T>) > LDSMAX) ? LDSMAX / (N * (int)sizeof(c2<T>)) : C1;
+  static constexpr int WG = C * TEAM;
+};
+
+template <typename T, int N>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, ColGeom<T, N>::WG)))
+col_kernel(ColArgs<T> a) {
+  using G = ColGeom<T, N>;
+  constexpr int E = G::E, TEAM = G::TEAM, C = G::C;
+  __shared__ c2<T> lds[N * C];
+  __shared__ double red[2 * (G::WG / 64 + 1)];
+  const int lane = threadIdx.x;
+  const int cc = lane % C;
+  const int t = lane / C;
+  const int col = blockIdx.x * C + cc;
+  const int o = blockIdx.y;
+  const bool active = col < a.ncols;
+  const long long base = (long long)o * a.os + (active ? col : 0);
+  c2<T>* my = lds + cc;
+  const int F = a.F;
+
+  auto load = [&](const c2<T>* src, c2<T>* v) {
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      v[m] = active ? src[base + (long long)(t + TEAM * m) * a.ls] : mk<T>(T(0), T(0));
+  };
+  auto store = [&](c2<T>* dst, const c2<T>* v) {
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) dst[base + (long long)(t + TEAM * m) * a.ls] = v[m];
+    }
+  };
+  const T kc = a.kcol[active ? col : 0] + (a.kouter ? a.kouter[o] : T(0));
+
+  c2<T> v[E];
+  if (a.mode == COL_FWD || a.mode == COL_INV) {
+    for (int f = 0; f < F; ++f) {
+      load(a.src + f * a.fs_src, v);
+      if (a.mode == COL_FWD) team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
+      else team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
+      store(a.dst + f * a.fs_dst, v);
+    }
+  } else if (a.mode == COL_UPDATE) {
+    // c: (c^ - dt M k2 g^) / (1 + dt M kappa_c k2^2), the k = 0 mode held in double
+    c2<T> g[E];
+    load(a.src, v);
+    load(a.src + a.fs_src, g);
+    team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
+    team_fft<T, N, E, false, C>(g, t, my, a.tw, 1);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = t + TEAM * m;
+      const T k2 = kc + a.kaxis[e];
+      const T D = a.invP / (T(1) + a.dtMkc * k2 * k2);
+      const T s = a.dtM * k2;
+      v[m] = mk<T>((v[m].x - s * g[m].x) * D, (v[m].y - s * g[m].y) * D);
+      if (col == 0 && o == 0 && e == 0) v[m] = mk<T>(T(*a.mean_c), T(0));
+    }
+    team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
+    store(a.dst, v);
+    // eta_i: b^ / (1 + dt L kappa_eta k2)
+    for (int f = 1; f < F; ++f) {
+      load(a.src + (f + 1) * a.fs_src, v);
+      team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const T k2 = kc + a.kaxis[t + TEAM * m];
+        const T D = a.invP / (T(1) + a.dtLke * k2);
+        v[m] = mk<T>(v[m].x * D, v[m].y * D);
+      }
+      team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
+      store(a.dst + f * a.fs_dst, v);
+    }
+  } else if (a.mode == COL_ADJ) {
+    // lambda^ -> a_c = D_c lambda_c^, b_c = D_c k2 lambda_c^, a_i = D_eta lambda_i^
+    c2<T> b[E];
+    load(a.src, v);
+    team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const T k2 = kc + a.kaxis[t + TEAM * m];
+      const T D = a.invP / (T(1) + a.dtMkc * k2 * k2);
+      v[m] = mk<T>(v[m].x * D, v[m].y * D);
+      b[m] = mk<T>(v[m].x * k2, v[m].y * k2);
+    }
+    team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
+    store(a.dst, v);
+    team_fft<T, N, E, true, C>(b, t, my, a.tw, 1);
+    store(a.dst + a.fs_dst, b);
+    for (int f = 1; f < F; ++f) {
+      load(a.src + f * a.fs_src, v);
+      team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const T k2 = kc + a.kaxis[t + TEAM * m];
+        const T D = a.invP / (T(1) + a.dtLke * k2);
+        v[m] = mk<T>(v[m].x * D, v[m].y * D);
+      }
+      team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
+      store(a.dst + (f + 1) * a.fs_dst, v);
+    }
+  } else {  // COL_ENERGY
+    double acc[2] = {0.0, 0.0};
+    const double wcol = (col == 0 || col == a.nyq) ? 1.0 : 2.0;
+    for (int f = 0; f < F; ++f) {
+      load(a.src + f * a.fs_src, v);
+      team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
+      if (active) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const double k2 = double(kc) + double(a.kaxis[t + TEAM * m]);
+          const double re = double(v[m].x), im = double(v[m].y);
+          acc[f == 0 ? 0 : 1] += wcol * k2 * (re * re + im * im);
+        }
+      }
+    }
+    block_sum<2>(acc, red);
+    if (threadIdx.x == 0) {
+      const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+      a.partials[2 * b + 0] = acc[0];
+      a.partials[2 * b + 1] = acc[1];
+    }
+  }
+}
+
+// Explicit FD step and FD energy (k_fd.hip).
+template <typename T>
+struct FdArgs {
+  const T* in;
+  T* out;
+  T* mu;
+  double* partials;
+  long long P;  // points per field
+  int nx, ny, nz, lx, ly, ndim, F;
+  T ix2, iy2, iz2;  // 1 / dx_d^2
+  T dtM, kc, dtL, ke;
+  double ix, iy, iz;  // 1 / dx_d
+  FeParams<T> fe;
+};
+
+// Single work-group fixed-order sum of `n` records of `width` doubles:
+// out[i] = scale[i] * sum_r partials[r * width + i].
+__global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ partials, int n,
+                                                     int width, double* __restrict__ out,
+                                                     double s0, double s1, double s2, double s3);
+
+}  // namespace pf

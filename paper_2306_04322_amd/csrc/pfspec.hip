@@ -1,0 +1,655 @@
+// libpfspec host runtime: configuration checks, plan tables, workspace
+// layout, launch sequencing on the caller's stream, and the C ABI of
+// include/pfspec.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pfspec.h"
+#include "pf_kernels.h"
+#include "pf_launch.h"
+
+using namespace pf;
+
+namespace {
+
+thread_local std::string g_err;
+
+pf_status fail(pf_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+bool is_pow2(long long n) { return n > 0 && (n & (n - 1)) == 0; }
+int log2i(long long n) {
+  int l = 0;
+  while ((1LL << l) < n) ++l;
+  return l;
+}
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+enum { PROF_ROW = 0, PROF_COL = 1, PROF_FD = 2, PROF_RED = 3, PROF_ADJ = 4, PROF_NCLS = 5 };
+
+struct ProfRec {
+  hipEvent_t a, b;
+  int cls;
+};
+
+}  // namespace
+
+struct pf_handle {
+  pf_config cfg;
+  int nd, nx, ny, nz, F, p, nxh, Sx, rows;
+  long long P;
+  size_t es;  // bytes per real element
+  double M, kc, L, ke;
+  double dV;
+  // host tables in double: twiddles (re, im interleaved) and |xi|^2 per axis
+  std::vector<double> tw[3], kt[3];
+  // workspace layout (byte offsets)
+  size_t off_B, off_S, off_tw[3], off_k[3], off_part, off_scal, ws_need;
+  size_t spec_field;  // complex elements per x-spectrum field
+  long long nparts;
+  std::vector<unsigned char> staging;
+  void* fields = nullptr;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  // profiling
+  bool prof_on = false;
+  std::vector<ProfRec> prof_pool;
+  size_t prof_used = 0;
+};
+
+namespace {
+
+int prof_begin(pf_handle* h, int cls) {
+  if (!h->prof_on) return -1;
+  if (h->prof_used == h->prof_pool.size()) {
+    if (h->prof_pool.size() >= 200000) return -1;
+    ProfRec r;
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+    h->prof_pool.push_back(r);
+  }
+  const int i = int(h->prof_used++);
+  h->prof_pool[i].cls = cls;
+  (void)hipEventRecord(h->prof_pool[i].a, h->stream);
+  return i;
+}
+void prof_end(pf_handle* h, int i) {
+  if (i >= 0) (void)hipEventRecord(h->prof_pool[i].b, h->stream);
+}
+
+pf_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(PF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return PF_OK;
+}
+
+void axis_tables(int n, double dx, int kmode, bool half, std::vector<double>& tw,
+                 std::vector<double>& kt) {
+  tw.resize(2 * size_t(n));
+  for (int q = 0; q < n; ++q) {
+    const long double ang = -2.0L * 3.14159265358979323846264338327950288L * q / n;
+    tw[2 * q] = double(cosl(ang));
+    tw[2 * q + 1] = double(sinl(ang));
+  }
+  const int nk = half ? n / 2 + 1 : n;
+  kt.resize(nk);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < nk; ++i) {
+    const int m = (i <= n / 2) ? i : i - n;  // Eq. (16): [0..N/2, -(N/2-1)..-1]
+    const double xi = 2.0 * pi * m / (n * dx);
+    double v;
+    if (kmode == PF_K_SPECTRAL) v = xi * xi;
+    else if (kmode == PF_K_FD2) v = -2.0 * (std::cos(dx * xi) - 1.0) / (dx * dx);
+    else v = -(16.0 * std::cos(dx * xi) - std::cos(2.0 * dx * xi) - 15.0) / (6.0 * dx * dx);
+    kt[i] = v;
+  }
+}
+
+template <typename T>
+FeParams<T> fe_params(const pf_handle* h) {
+  FeParams<T> f;
+  f.kind = (h->cfg.fe == PF_FE_PAPER) ? FE_PAPER : FE_POLY;
+  for (int i = 0; i < 12; ++i) f.k[i] = T(h->cfg.fe_coef[i]);
+  return f;
+}
+
+template <typename T>
+const c2<T>* twp(const pf_handle* h, int ax) {
+  return reinterpret_cast<const c2<T>*>(h->ws + h->off_tw[ax]);
+}
+template <typename T>
+const T* ktp(const pf_handle* h, int ax) {
+  return reinterpret_cast<const T*>(h->ws + h->off_k[ax]);
+}
+template <typename T>
+c2<T>* specB(const pf_handle* h) { return reinterpret_cast<c2<T>*>(h->ws + h->off_B); }
+template <typename T>
+c2<T>* specS(const pf_handle* h) { return reinterpret_cast<c2<T>*>(h->ws + h->off_S); }
+double* partials(const pf_handle* h) { return reinterpret_cast<double*>(h->ws + h->off_part); }
+double* scal(const pf_handle* h) { return reinterpret_cast<double*>(h->ws + h->off_scal); }
+
+// scalar slots in the workspace
+enum { SC_FSUM = 0, SC_MEANC = 1, SC_EN = 4, SC_DPAR = 12 };
+
+template <typename T>
+XArgs<T> xargs(const pf_handle* h) {
+  XArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.twx = twp<T>(h, 0);
+  a.partials = partials(h);
+  a.fs_real = h->P;
+  a.fs_spec = (long long)h->spec_field;
+  a.rows = h->rows;
+  a.Sx = h->Sx;
+  a.F = h->F;
+  a.fe = fe_params<T>(h);
+  return a;
+}
+
+template <typename T>
+pf_status row(pf_handle* h, XArgs<T>& a, int* nblk) {
+  const int pi = prof_begin(h, PROF_ROW);
+  const int g = row_launch<T>(h->nx, h->p, a, h->stream);
+  prof_end(h, pi);
+  if (g < 0) return fail(PF_ERR_UNSUPPORTED, "row pass: unsupported Nx");
+  if (nblk) *nblk = g;
+  return check_launch("row pass");
+}
+
+template <typename T>
+ColArgs<T> cargs(const pf_handle* h, double dt) {
+  ColArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.kcol = ktp<T>(h, 0);
+  a.mean_c = scal(h) + SC_MEANC;
+  a.partials = partials(h);
+  a.fs_src = a.fs_dst = (long long)h->spec_field;
+  a.ncols = h->nxh;
+  a.nyq = h->nx / 2;
+  a.F = h->F;
+  a.dtM = T(dt * h->M);
+  a.dtMkc = T(dt * h->M * h->kc);
+  a.dtL = T(dt * h->L);
+  a.dtLke = T(dt * h->L * h->ke);
+  a.invP = T(1.0 / double(h->P));
+  return a;
+}
+
+// Strided-axis pass.  axis 1 = y, axis 2 = z.
+template <typename T>
+pf_status col(pf_handle* h, ColArgs<T>& a, int axis, int* nblk) {
+  const long long plane = (long long)h->ny * h->Sx;
+  int n, nouter;
+  if (axis == 1) {
+    n = h->ny;
+    a.ls = h->Sx;
+    a.os = plane;
+    nouter = h->nz;
+    a.tw = twp<T>(h, 1);
+    a.kaxis = ktp<T>(h, 1);
+    a.kouter = (h->nd == 3) ? ktp<T>(h, 2) : nullptr;
+  } else {
+    n = h->nz;
+    a.ls = plane;
+    a.os = h->Sx;
+    nouter = h->ny;
+    a.tw = twp<T>(h, 2);
+    a.kaxis = ktp<T>(h, 2);
+    a.kouter = ktp<T>(h, 1);
+  }
+  const int pi = prof_begin(h, PROF_COL);
+  const int g = col_launch<T>(n, nouter, a, h->stream);
+  prof_end(h, pi);
+  if (g < 0) return fail(PF_ERR_UNSUPPORTED, "column pass: unsupported length");
+  if (nblk) *nblk = g;
+  return check_launch("column pass");
+}
+
+pf_status reduce(pf_handle* h, int n, int width, double* out, double s0, double s1, double s2,
+                 double s3) {
+  const double sc[4] = {s0, s1, s2, s3};
+  const int pi = prof_begin(h, PROF_RED);
+  reduce_launch(partials(h), n, width, out, sc, h->stream);
+  prof_end(h, pi);
+  return check_launch("reduction");
+}
+
+#define PF_TRY(x)                  \
+  do {                             \
+    pf_status _s = (x);            \
+    if (_s != PF_OK) return _s;    \
+  } while (0)
+
+// k-space update between forward and inverse transforms along the strided
+// axes: 2D one column pass; 3D y-forward, z update, y-inverse.
+template <typename T>
+pf_status spectral_update(pf_handle* h, double dt) {
+  ColArgs<T> a = cargs<T>(h, dt);
+  if (h->nd == 2) {
+    a.src = specB<T>(h);
+    a.dst = specS<T>(h);
+    a.mode = COL_UPDATE;
+    return col<T>(h, a, 1, nullptr);
+  }
+  a.src = specB<T>(h);
+  a.dst = specB<T>(h);
+  a.mode = COL_FWD;
+  a.F = h->F + 1;
+  PF_TRY(col<T>(h, a, 1, nullptr));
+  a.F = h->F;
+  a.dst = specS<T>(h);
+  a.mode = COL_UPDATE;
+  PF_TRY(col<T>(h, a, 2, nullptr));
+  a.src = specS<T>(h);
+  a.dst = specS<T>(h);
+  a.mode = COL_INV;
+  return col<T>(h, a, 1, nullptr);
+}
+
+// nsteps FS steps from real fields `uin` to real fields `uout` (may alias).
+// When `store` is non-null, the states u^1..u^n are also written there
+// (field-set stride F*P), which is how the adjoint recomputes a segment.
+template <typename T>
+pf_status fs_run(pf_handle* h, double dt, long long nsteps, const T* uin, T* uout, T* store) {
+  if (nsteps == 0) {
+    if (uin != uout)
+      if (hipMemcpyAsync(uout, uin, h->es * h->F * h->P, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+        return fail(PF_ERR_HIP, "hipMemcpyAsync failed");
+    return PF_OK;
+  }
+  XArgs<T> x = xargs<T>(h);
+  x.dtL = T(dt * h->L);
+  x.u_in = uin;
+  x.b_out = specB<T>(h);
+  x.flags = X_LOAD_REAL | X_FWD_DERIV | X_ESUM;
+  int nb = 0;
+  PF_TRY(row<T>(h, x, &nb));
+  PF_TRY(reduce(h, nb, 2, scal(h) + SC_FSUM, 1.0, 1.0 / double(h->P), 0, 0));
+  const long long fsz = (long long)h->F * h->P;
+  for (long long s = 0; s < nsteps; ++s) {
+    PF_TRY(spectral_update<T>(h, dt));
+    XArgs<T> y = xargs<T>(h);
+    y.dtL = T(dt * h->L);
+    y.s_in = specS<T>(h);
+    const bool last = (s == nsteps - 1);
+    if (store) {
+      y.u_out = store + s * fsz;
+      y.flags = X_STORE_REAL | (last ? 0 : X_FWD_DERIV);
+    } else {
+      y.u_out = uout;
+      y.flags = last ? X_STORE_REAL : X_FWD_DERIV;
+    }
+    y.b_out = specB<T>(h);
+    PF_TRY(row<T>(h, y, nullptr));
+  }
+  if (store && uout) {
+    if (hipMemcpyAsync(uout, store + (nsteps - 1) * fsz, h->es * fsz, hipMemcpyDeviceToDevice,
+                       h->stream) != hipSuccess)
+      return fail(PF_ERR_HIP, "hipMemcpyAsync failed");
+  }
+  return PF_OK;
+}
+
+template <typename T>
+FdArgs<T> fdargs(const pf_handle* h, double dt) {
+  FdArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.P = h->P;
+  a.nx = h->nx;
+  a.ny = h->ny;
+  a.nz = h->nz;
+  a.lx = log2i(h->nx);
+  a.ly = log2i(h->ny);
+  a.ndim = h->nd;
+  a.F = h->F;
+  const double* d = h->cfg.dx;
+  a.ix2 = T(1.0 / (d[0] * d[0]));
+  a.iy2 = T(1.0 / (d[1] * d[1]));
+  a.iz2 = T(h->nd == 3 ? 1.0 / (d[2] * d[2]) : 0.0);
+  a.ix = 1.0 / d[0];
+  a.iy = 1.0 / d[1];
+  a.iz = h->nd == 3 ? 1.0 / d[2] : 0.0;
+  a.dtM = T(dt * h->M);
+  a.kc = T(h->kc);
+  a.dtL = T(dt * h->L);
+  a.ke = T(h->ke);
+  a.fe = fe_params<T>(h);
+  a.partials = partials(h);
+  return a;
+}
+
+template <typename T>
+pf_status fd_run(pf_handle* h, double dt, long long nsteps) {
+  if (nsteps == 0) return PF_OK;
+  T* A = static_cast<T*>(h->fields);
+  T* Bf = reinterpret_cast<T*>(h->ws + h->off_B);  // FD buffers share the FS spectra area
+  T* mu = Bf + (long long)h->F * h->P;
+  const size_t bytes = h->es * h->F * h->P;
+  T* cur = A;
+  T* nxt = Bf;
+  if (nsteps & 1) {
+    if (hipMemcpyAsync(Bf, A, bytes, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+      return fail(PF_ERR_HIP, "hipMemcpyAsync failed");
+    cur = Bf;
+    nxt = A;
+  }
+  FdArgs<T> a = fdargs<T>(h, dt);
+  a.mu = mu;
+  for (long long s = 0; s < nsteps; ++s) {
+    a.in = cur;
+    a.out = nxt;
+    int pi = prof_begin(h, PROF_FD);
+    fd_launch<T>(0, h->p, a, h->stream);
+    fd_launch<T>(1, h->p, a, h->stream);
+    prof_end(h, pi);
+    PF_TRY(check_launch("FD step"));
+    T* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  return PF_OK;
+}
+
+template <typename T>
+pf_status energy_run(pf_handle* h, int scheme, double out[5]) {
+  double* sc = scal(h) + SC_EN;
+  const double dV = h->dV;
+  if (scheme == 0) {
+    XArgs<T> x = xargs<T>(h);
+    x.u_in = static_cast<const T*>(h->fields);
+    x.b_out = specB<T>(h);
+    x.flags = X_LOAD_REAL | X_FWD_RAW | X_ESUM;
+    int nb = 0;
+    PF_TRY(row<T>(h, x, &nb));
+    PF_TRY(reduce(h, nb, 2, sc, dV, dV, 0, 0));
+    ColArgs<T> a = cargs<T>(h, 0.0);
+    a.src = specB<T>(h);
+    a.dst = specB<T>(h);
+    int ng = 0;
+    if (h->nd == 3) {
+      a.mode = COL_FWD;
+      PF_TRY(col<T>(h, a, 1, nullptr));
+      a.mode = COL_ENERGY;
+      PF_TRY(col<T>(h, a, 2, &ng));
+    } else {
+      a.mode = COL_ENERGY;
+      PF_TRY(col<T>(h, a, 1, &ng));
+    }
+    const double s = dV / double(h->P);
+    PF_TRY(reduce(h, ng, 2, sc + 2, 0.5 * h->kc * s, 0.5 * h->ke * s, 0, 0));
+  } else {
+    FdArgs<T> a = fdargs<T>(h, 0.0);
+    a.in = static_cast<const T*>(h->fields);
+    const int pi = prof_begin(h, PROF_FD);
+    const int ng = fd_launch<T>(2, h->p, a, h->stream);
+    prof_end(h, pi);
+    PF_TRY(check_launch("FD energy"));
+    // partials: {f, grad c, grad eta, c} -> sc[0..3]; reorder below
+    PF_TRY(reduce(h, ng, 4, sc, dV, 0.5 * h->kc * dV, 0.5 * h->ke * dV, dV));
+  }
+  double hv[4];
+  if (hipMemcpyAsync(hv, sc, sizeof(hv), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return fail(PF_ERR_HIP, std::string("energy readback: ") + hipGetErrorString(hipGetLastError()));
+  double chem, mass, gc, ge;
+  if (scheme == 0) {
+    chem = hv[0];
+    mass = hv[1];
+    gc = hv[2];
+    ge = hv[3];
+  } else {
+    chem = hv[0];
+    gc = hv[1];
+    ge = hv[2];
+    mass = hv[3];
+  }
+  out[0] = chem + gc + ge;
+  out[1] = chem;
+  out[2] = gc;
+  out[3] = ge;
+  out[4] = mass;
+  for (int i = 0; i < 5; ++i)
+    if (!std::isfinite(out[i])) return fail(PF_ERR_NONFINITE, "free energy is not finite");
+  return PF_OK;
+}
+
+template <typename T>
+void fill_staging(pf_handle* h) {
+  h->staging.assign(h->ws_need - h->off_tw[0], 0);
+  unsigned char* base = h->staging.data() - h->off_tw[0];
+  for (int ax = 0; ax < 3; ++ax) {
+    c2<T>* tw = reinterpret_cast<c2<T>*>(base + h->off_tw[ax]);
+    for (size_t q = 0; q < h->tw[ax].size() / 2; ++q) {
+      tw[q].x = T(h->tw[ax][2 * q]);
+      tw[q].y = T(h->tw[ax][2 * q + 1]);
+    }
+    T* kt = reinterpret_cast<T*>(base + h->off_k[ax]);
+    for (size_t i = 0; i < h->kt[ax].size(); ++i) kt[i] = T(h->kt[ax][i]);
+  }
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_create(const pf_config* cfg, pf_handle** out) {
+  if (!out) return fail(PF_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(PF_ERR_INVALID, "cfg is NULL");
+  const pf_config& c = *cfg;
+  if (c.ndim != 2 && c.ndim != 3) return fail(PF_ERR_INVALID, "ndim must be 2 or 3");
+  const int maxn = c.ndim == 2 ? 4096 : 1024;
+  for (int d = 0; d < c.ndim; ++d) {
+    if (!is_pow2(c.n[d]) || c.n[d] < 8 || c.n[d] > maxn)
+      return fail(PF_ERR_INVALID, "grid sizes must be powers of two in [8, " + std::to_string(maxn) + "]");
+    if (!finite_pos(c.dx[d])) return fail(PF_ERR_INVALID, "dx must be finite and > 0");
+  }
+  if (c.ndim == 2 && c.n[2] != 1) return fail(PF_ERR_INVALID, "n[2] must be 1 in 2D");
+  if (c.p < 1 || c.p > 8) return fail(PF_ERR_INVALID, "p must be in [1, 8]");
+  if (c.prec != PF_F32 && c.prec != PF_F64) return fail(PF_ERR_INVALID, "prec must be PF_F32 or PF_F64");
+  if (c.fe != PF_FE_POLY && c.fe != PF_FE_PAPER) return fail(PF_ERR_INVALID, "unknown free energy");
+  if (c.kmode != PF_K_SPECTRAL && c.kmode != PF_K_FD2 && c.kmode != PF_K_FD4)
+    return fail(PF_ERR_INVALID, "unknown kmode");
+  if (!finite_pos(c.M) || !finite_pos(c.kappa_c) || !finite_pos(c.L) || !finite_pos(c.kappa_eta))
+    return fail(PF_ERR_INVALID, "M, kappa_c, L, kappa_eta must be finite and > 0");
+  for (int i = 0; i < 12; ++i)
+    if (!std::isfinite(c.fe_coef[i])) return fail(PF_ERR_INVALID, "fe_coef must be finite");
+
+  pf_handle* h = new (std::nothrow) pf_handle;
+  if (!h) return fail(PF_ERR_INVALID, "out of host memory");
+  h->cfg = c;
+  h->nd = c.ndim;
+  h->nx = c.n[0];
+  h->ny = c.n[1];
+  h->nz = c.ndim == 3 ? c.n[2] : 1;
+  h->cfg.n[2] = h->nz;
+  h->p = c.p;
+  h->F = c.p + 1;
+  h->nxh = h->nx / 2 + 1;
+  h->es = c.prec == PF_F32 ? 4 : 8;
+  const int align_c = c.prec == PF_F32 ? 16 : 8;  // complex values per 128 bytes
+  h->Sx = (h->nxh + align_c - 1) / align_c * align_c;
+  h->rows = h->ny * h->nz;
+  h->P = (long long)h->nx * h->ny * h->nz;
+  h->M = c.M;
+  h->kc = c.kappa_c;
+  h->L = c.L;
+  h->ke = c.kappa_eta;
+  h->dV = c.dx[0] * c.dx[1] * (c.ndim == 3 ? c.dx[2] : 1.0);
+  h->stream = static_cast<hipStream_t>(c.stream);
+  const int ns[3] = {h->nx, h->ny, h->nz};
+  for (int ax = 0; ax < 3; ++ax) {
+    const double dx = (ax < c.ndim) ? c.dx[ax] : 1.0;
+    axis_tables(ns[ax], dx, c.kmode, ax == 0, h->tw[ax], h->kt[ax]);
+  }
+  // workspace layout
+  const size_t cbytes = 2 * h->es;
+  h->spec_field = size_t(h->rows) * h->Sx;
+  size_t off = 0;
+  h->off_B = off;
+  off = align256(off + size_t(h->F + 1) * h->spec_field * cbytes);
+  h->off_S = off;
+  off = align256(off + size_t(h->F + 1) * h->spec_field * cbytes);
+  for (int ax = 0; ax < 3; ++ax) {
+    h->off_tw[ax] = off;
+    off = align256(off + size_t(ns[ax]) * cbytes);
+  }
+  for (int ax = 0; ax < 3; ++ax) {
+    h->off_k[ax] = off;
+    off = align256(off + h->kt[ax].size() * h->es);
+  }
+  long long np = h->rows;
+  np = std::max<long long>(np, (long long)h->nxh * std::max(h->ny, h->nz));
+  np = std::max<long long>(np, (h->P + 255) / 256);
+  h->nparts = np;
+  h->off_part = off;
+  off = align256(off + size_t(np) * 4 * sizeof(double));
+  h->off_scal = off;
+  off = align256(off + 64 * sizeof(double));
+  h->ws_need = off;
+  *out = h;
+  return PF_OK;
+}
+
+void pf_destroy(pf_handle* h) {
+  if (!h) return;
+  for (auto& r : h->prof_pool) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  delete h;
+}
+
+size_t pf_workspace_bytes(const pf_handle* h) { return h ? h->ws_need : 0; }
+
+size_t pf_segment_bytes(const pf_handle* h, int64_t k) {
+  if (!h || k < 0) return 0;
+  return size_t(k) * size_t(h->F) * size_t(h->P) * h->es;
+}
+
+pf_status pf_bind(pf_handle* h, void* fields, void* workspace, size_t workspace_bytes) {
+  if (!h) return fail(PF_ERR_INVALID, "handle is NULL");
+  if (!fields || !workspace) return fail(PF_ERR_INVALID, "fields and workspace must be non-NULL");
+  if ((reinterpret_cast<uintptr_t>(fields) & 255) || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(PF_ERR_INVALID, "fields and workspace must be 256-byte aligned");
+  if (workspace_bytes < h->ws_need)
+    return fail(PF_ERR_NOMEM, "workspace too small: need " + std::to_string(h->ws_need) + " bytes");
+  h->fields = fields;
+  h->ws = static_cast<char*>(workspace);
+  if (h->es == 4) fill_staging<float>(h);
+  else fill_staging<double>(h);
+  if (hipMemcpyAsync(h->ws + h->off_tw[0], h->staging.data(), h->staging.size(),
+                     hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return fail(PF_ERR_HIP, std::string("table upload: ") + hipGetErrorString(hipGetLastError()));
+  return PF_OK;
+}
+
+pf_status pf_set_params(pf_handle* h, double M, double kappa_c, double L, double kappa_eta) {
+  if (!h) return fail(PF_ERR_INVALID, "handle is NULL");
+  if (!finite_pos(M) || !finite_pos(kappa_c) || !finite_pos(L) || !finite_pos(kappa_eta))
+    return fail(PF_ERR_INVALID, "M, kappa_c, L, kappa_eta must be finite and > 0");
+  h->M = M;
+  h->kc = kappa_c;
+  h->L = L;
+  h->ke = kappa_eta;
+  return PF_OK;
+}
+
+pf_status pf_set_stream(pf_handle* h, void* stream) {
+  if (!h) return fail(PF_ERR_INVALID, "handle is NULL");
+  h->stream = static_cast<hipStream_t>(stream);
+  return PF_OK;
+}
+
+static pf_status check_step(pf_handle* h, double dt, int64_t nsteps) {
+  if (!h) return fail(PF_ERR_INVALID, "handle is NULL");
+  if (!h->ws) return fail(PF_ERR_INVALID, "pf_bind has not been called");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(PF_ERR_INVALID, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(PF_ERR_INVALID, "nsteps must be >= 0");
+  return PF_OK;
+}
+
+pf_status pf_step_fs(pf_handle* h, double dt, int64_t nsteps) {
+  PF_TRY(check_step(h, dt, nsteps));
+  if (h->es == 4) {
+    float* u = static_cast<float*>(h->fields);
+    return fs_run<float>(h, dt, nsteps, u, u, nullptr);
+  }
+  double* u = static_cast<double*>(h->fields);
+  return fs_run<double>(h, dt, nsteps, u, u, nullptr);
+}
+
+pf_status pf_step_fd(pf_handle* h, double dt, int64_t nsteps) {
+  PF_TRY(check_step(h, dt, nsteps));
+  return h->es == 4 ? fd_run<float>(h, dt, nsteps) : fd_run<double>(h, dt, nsteps);
+}
+
+pf_status pf_energy(pf_handle* h, int32_t scheme, double out[5]) {
+  if (!h || !out) return fail(PF_ERR_INVALID, "handle and out must be non-NULL");
+  if (!h->ws) return fail(PF_ERR_INVALID, "pf_bind has not been called");
+  if (scheme != 0 && scheme != 1) return fail(PF_ERR_INVALID, "scheme must be 0 (FS) or 1 (FD)");
+  return h->es == 4 ? energy_run<float>(h, scheme, out) : energy_run<double>(h, scheme, out);
+}
+
+pf_status pf_adjoint_fs(pf_handle* h, double dt, int64_t k, const void* u_ckpt, void* lambda,
+                        double dparams[4], void* seg_store) {
+  (void)dt; (void)k; (void)u_ckpt; (void)lambda; (void)dparams; (void)seg_store;
+  if (!h) return fail(PF_ERR_INVALID, "handle is NULL");
+  return fail(PF_ERR_UNSUPPORTED, "adjoint not built yet");
+}
+
+pf_status pf_profile_enable(pf_handle* h, int32_t enable) {
+  if (!h) return fail(PF_ERR_INVALID, "handle is NULL");
+  h->prof_on = enable != 0;
+  h->prof_used = 0;
+  return PF_OK;
+}
+
+pf_status pf_profile_read(pf_handle* h, int32_t kernel_class, int64_t* count, double* total_ms) {
+  if (!h || !count || !total_ms) return fail(PF_ERR_INVALID, "NULL argument");
+  if (kernel_class < 0 || kernel_class >= PROF_NCLS) return fail(PF_ERR_INVALID, "bad kernel class");
+  if (hipStreamSynchronize(h->stream) != hipSuccess)
+    return fail(PF_ERR_HIP, std::string("sync: ") + hipGetErrorString(hipGetLastError()));
+  int64_t n = 0;
+  double ms = 0.0;
+  for (size_t i = 0; i < h->prof_used; ++i) {
+    if (h->prof_pool[i].cls != kernel_class) continue;
+    float e = 0.f;
+    if (hipEventElapsedTime(&e, h->prof_pool[i].a, h->prof_pool[i].b) != hipSuccess)
+      return fail(PF_ERR_HIP, "hipEventElapsedTime failed");
+    ms += e;
+    ++n;
+  }
+  *count = n;
+  *total_ms = ms;
+  return PF_OK;
+}
+
+const char* pf_status_string(pf_status s) {
+  switch (s) {
+    case PF_OK: return "PF_OK";
+    case PF_ERR_INVALID: return "PF_ERR_INVALID";
+    case PF_ERR_UNSUPPORTED: return "PF_ERR_UNSUPPORTED";
+    case PF_ERR_NOMEM: return "PF_ERR_NOMEM";
+    case PF_ERR_HIP: return "PF_ERR_HIP";
+    case PF_ERR_NONFINITE: return "PF_ERR_NONFINITE";
+  }
+  return "unknown pf_status";
+}
+
+const char* pf_last_error(void) { return g_err.c_str(); }
+
+int32_t pf_version(void) { return 100; }
+
+}  // extern "C"

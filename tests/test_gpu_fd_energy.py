@@ -1,0 +1,109 @@
+"""GPU parity of the FD step (pf_step_fd) and the free-energy reductions
+(pf_energy) against the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+from oracle import energy as oen
+from oracle import fd as ofd
+from oracle import fs as ofs
+from paper_2306_04322_amd import inputs as I
+from parity_util import announce, fp32_rounded, gpu_or_fail, max_rel, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-4}
+
+
+def _solver(cfg, prec, u0):
+    gpu_or_fail()
+    from paper_2306_04322_amd.pfspec import Solver
+    s = Solver(cfg, prec)
+    s.set_fields(u0)
+    return s
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fd_workload_parity(prec):
+    cfg, w = I.workload_config("WO")
+    u0 = I.workload_ic(cfg, w)
+    if prec == "f32":
+        u0 = fp32_rounded(u0)
+    announce("fd parity WO", prec)
+    s = _solver(cfg, prec, u0)
+    s.step_fd(w["dt_fd"], 101)  # odd count exercises the ping-pong copy
+    s.step_fd(w["dt_fd"], 99)
+    got = s.get_fields()
+    ref = ofd.fd_run(u0, cfg, w["dt_fd"], 200)
+    errs = rel_l2(got, ref)
+    print("FD WO", prec, errs)
+    assert max_rel(errs) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("ndim,n,p", [(2, (32, 8), 1), (2, (16, 64), 4), (3, (16, 8, 32), 4),
+                                      (3, (8, 8, 8), 8)])
+def test_fd_shapes_parity(ndim, n, p, prec):
+    dx = (1.0, 0.8, 1.2)[:ndim]
+    cfg = I.make_config(ndim, n, dx, p, I.PAPER_FE)
+    u0 = I.random_ic(cfg, seed=9)
+    if prec == "f32":
+        u0 = fp32_rounded(u0)
+    announce("fd shapes", ndim, n, p, prec)
+    s = _solver(cfg, prec, u0)
+    s.step_fd(2e-4, 20)
+    got = s.get_fields()
+    ref = ofd.fd_run(u0, cfg, 2e-4, 20)
+    assert max_rel(rel_l2(got, ref)) <= (1e-12 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("scheme", ["fs", "fd"])
+@pytest.mark.parametrize("case", ["WO", "rand2d", "rand3d", "poly"])
+def test_energy_parity(case, scheme, prec):
+    if case == "WO":
+        cfg, w = I.workload_config("WO")
+        u0 = I.workload_ic(cfg, w)
+    elif case == "rand2d":
+        cfg = I.make_config(2, (64, 128), (0.5, 1.5), 2, I.PAPER_FE, "fd4")
+        u0 = I.random_ic(cfg, 4)
+    elif case == "rand3d":
+        cfg = I.make_config(3, (16, 32, 8), 1.0, 4, I.PAPER_FE)
+        u0 = I.random_ic(cfg, 5, c0=0.45)
+    else:
+        cfg = I.make_config(2, 32, 1.0, 3, I.POLY_FE)
+        u0 = I.random_ic(cfg, 6)
+    if prec == "f32":
+        u0 = fp32_rounded(u0)
+    announce("energy", case, scheme, prec)
+    s = _solver(cfg, prec, u0)
+    got = s.energy(scheme)
+    ref = oen.energy(u0, cfg, scheme)
+    tol = 1e-12 if prec == "f64" else 2e-6
+    for i in range(5):
+        assert abs(got[i] - ref[i]) <= tol * max(abs(ref[i]), 1e-3 * abs(ref[0])), (i, got, ref)
+
+
+def test_energy_decreases_along_gpu_fs_run():
+    cfg, w = I.workload_config("WO")
+    u0 = I.workload_ic(cfg, w)
+    announce("energy monotone fs f64")
+    s = _solver(cfg, "f64", u0)
+    E = [s.energy("fs")[0]]
+    for _ in range(10):
+        s.step_fs(0.01, 20)
+        E.append(s.energy("fs")[0])
+    assert all(b <= a * (1 + 1e-13) for a, b in zip(E[:-1], E[1:]))
+
+
+def test_energy_reports_nonfinite():
+    gpu_or_fail()
+    from paper_2306_04322_amd.pfspec import PF_ERR_NONFINITE, PFError
+    cfg = I.make_config(2, 16, 1.0, 2, I.PAPER_FE)
+    u0 = I.random_ic(cfg, 1)
+    u0[0, 3, 4] = np.nan
+    announce("energy nonfinite")
+    s = _solver(cfg, "f64", u0)
+    with pytest.raises(PFError) as ei:
+        s.energy("fd")
+    assert ei.value.status == PF_ERR_NONFINITE

@@ -1,0 +1,286 @@
+"""Benchmark of the semi-implicit Fourier-spectral (FS) phase-field step on
+one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+
+Headline: FS grid-point updates per second on 2D 1024 x 1024 with c + 4 eta
+(F = 5 fields), FP32, seeded synthetic initial state, the inputs resident in
+HBM before the timed region.  One "step" is one FS time step of the whole
+grid (free-energy derivatives, forward transforms, k-space solve, inverse
+transforms).  Exactly K steps are timed between two device
+synchronisations.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                average launch time (HIP events on the library's stream),
+                against 8 TB/s HBM
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
+  extras        FP64 path, 3D 256^3 FS (FP32, FP64), explicit FD step,
+                adjoint step cost, and the paper's own FS-vs-FD figures
+"""
+
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "FS grid-pt updates/s, 2D 1024² & 3D 256³, FP32 vs FP64; % HBM roofline"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(cfg, prec, kind):
+    """Compulsory HBM bytes of one launch of a pass over the whole grid.
+
+    Both passes of a 2D FS step read and write x-spectra only: the row pass
+    reads F x-spectra and writes F + 1, the column pass reads F + 1 and
+    writes F, each x-spectrum holding (Nx/2 + 1) complex values per row.
+    """
+    F = 1 + cfg["p"]
+    nx, ny = cfg["n"][0], cfg["n"][1]
+    nz = cfg["n"][2] if cfg["ndim"] == 3 else 1
+    s = 4 if prec == "f32" else 8
+    spec = (nx // 2 + 1) * ny * nz * 2 * s  # one x-spectrum field
+    if kind in ("row", "col"):
+        return (2 * F + 1) * spec
+    raise ValueError(kind)
+
+
+def time_fs(solver, dt, steps, warmup, torch):
+    if warmup:
+        solver.step_fs(dt, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step_fs(dt, steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def kernel_profile(solver, dt, steps, torch):
+    from paper_2306_04322_amd import pfspec as P
+    P.pf_profile_enable(solver.h, True)
+    solver.step_fs(dt, steps)
+    out = {}
+    for name, cls in (("row", P.PROF_ROW), ("col", P.PROF_COL), ("reduce", P.PROF_RED)):
+        n, ms = P.pf_profile_read(solver.h, cls)
+        out[name] = (n, ms)
+    P.pf_profile_enable(solver.h, False)
+    return out
+
+
+def cpu_baseline(cfg, u0, dt, budget_s=20.0):
+    """FP64 oracle on the same workload, as many whole steps as fit the
+    budget (at least one), timed on one host core."""
+    import numpy as np
+    from oracle import fs as ofs
+    P = int(np.prod(u0.shape[1:]))
+    steps = 0
+    u = u0
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    while True:
+        u = ofs.fs_run(u, cfg, dt, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 50:
+            break
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    cores = max(1, int(round(cpu / el)))
+    return {"value": P * steps / el, "unit": "grid-pt updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d FS step(s) of the 2D 1024x1024, F=5 workload (FP64 NumPy oracle, own "
+                      "radix-2 FFT), %.1f s wall, %.1f s CPU" % (steps, el, cpu)}
+
+
+def traffic_from_profile(kind):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if the
+    kernel source is unchanged since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_w2_f32.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        from paper_2306_04322_amd.build import source_digest
+        if rec.get("source_digest") != source_digest():
+            return None
+        return rec.get(kind, {}).get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="headline and roofline only")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device copy (counter calibration)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the FS step is benchmarked on a single "
+              "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2306_04322_amd import inputs as I
+    from paper_2306_04322_amd.pfspec import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    cfg, w = I.workload_config("W2")
+    dt = w["dt_fs"]
+    u0 = I.workload_ic(cfg, w)
+    P = cfg["n"][0] * cfg["n"][1]
+    log("2D 1024^2 F=5 FP32: warmup", args.warmup, "timed", args.steps)
+    s32 = Solver(cfg, "f32")
+    s32.set_fields(u0)
+    t = time_fs(s32, dt, args.steps, args.warmup, torch)
+    value = P * args.steps / t
+    ms = 1e3 * t / args.steps
+    log("fp32 %.3f ms/step, %.3e pt-upd/s" % (ms, value))
+
+    prof = kernel_profile(s32, dt, min(args.steps, 500), torch)
+    avg = {k: (v[1] / v[0] if v[0] else 0.0) for k, v in prof.items()}
+    dom = "row" if prof["row"][1] >= prof["col"][1] else "col"
+    A = algorithmic_bytes(cfg, "f32", dom)
+    achieved = A / (avg[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(dom),
+            "kernel": "xpass_kernel<float,1024,4>" if dom == "row" else "col_kernel<float,1024>",
+            "algorithmic_bytes_per_launch": A,
+            "avg_launch_us": round(avg[dom] * 1e3, 3),
+            "other_kernel": {"name": "col" if dom == "row" else "row",
+                             "avg_launch_us": round(avg["col" if dom == "row" else "row"] * 1e3, 3),
+                             "achieved_GBs": round(algorithmic_bytes(cfg, "f32", "col" if dom == "row" else "row")
+                                                   / (avg["col" if dom == "row" else "row"] * 1e-3) / 1e9, 1)}}
+    log("roofline", roof)
+
+    out = {"metric": METRIC, "value": value, "unit": "grid-pt updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "FS step, 2D 1024x1024 periodic, dx=1, c + 4 eta (F=5), paper "
+                                  "f_chem, seeded uniform IC c=0.5+0.05U(-1,1), eta=0.1U(0,1), dt=0.1",
+                      "grid": [1024, 1024], "fields": 5, "dt": dt, "precision": "f32"},
+           "roofline": roof}
+    del s32
+    torch.cuda.empty_cache()
+
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = {"read": a.numel() * 4, "write": a.numel() * 4}
+        del a, b
+
+    if not args.no_extras:
+        extras = {}
+        s64 = Solver(cfg, "f64")
+        s64.set_fields(u0)
+        n64 = min(args.steps, 1000)
+        t64 = time_fs(s64, dt, n64, 50, torch)
+        v64 = P * n64 / t64
+        extras["fs_2d_1024_f64"] = {"value": v64, "ms_per_step": 1e3 * t64 / n64,
+                                    "fp32_over_fp64": value / v64}
+        log("fp64 %.3f ms/step; fp32/fp64 = %.2f" % (1e3 * t64 / n64, value / v64))
+        del s64
+        # explicit FD on the same grid and state (stable dt of the FD scheme)
+        sfd = Solver(cfg, "f32")
+        sfd.set_fields(u0)
+        sfd.step_fd(w["dt_fd"], 100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sfd.step_fd(w["dt_fd"], 2000)
+        torch.cuda.synchronize()
+        tfd = (time.perf_counter() - t0) / 2000
+        extras["fd_2d_1024_f32"] = {"value": P / tfd, "ms_per_step": 1e3 * tfd,
+                                    "fs_over_fd_time_per_step": (t / args.steps) / tfd}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            sfd.energy("fs")
+        extras["energy_2d_1024_f32_ms"] = 1e3 * (time.perf_counter() - t0) / 20
+        del sfd
+        torch.cuda.empty_cache()
+        # 3D 256^3, c + 4 eta
+        cfg3, w3 = I.workload_config("W3")
+        u3 = I.workload_ic(cfg3, w3)
+        P3 = 256 ** 3
+        for prec, n3 in (("f32", 200), ("f64", 100)):
+            s3 = Solver(cfg3, prec)
+            s3.set_fields(u3)
+            t3 = time_fs(s3, w3["dt_fs"], n3, 10, torch)
+            extras["fs_3d_256_" + prec] = {"value": P3 * n3 / t3, "ms_per_step": 1e3 * t3 / n3}
+            log("3D %s %.3f ms/step" % (prec, 1e3 * t3 / n3))
+            if prec == "f32":
+                s3.step_fd(w3["dt_fd"], 10)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s3.step_fd(w3["dt_fd"], 100)
+                torch.cuda.synchronize()
+                tf3 = (time.perf_counter() - t0) / 100
+                extras["fd_3d_256_f32"] = {"value": P3 / tf3, "ms_per_step": 1e3 * tf3}
+            del s3
+            torch.cuda.empty_cache()
+        extras["fs_3d_256_f32_over_f64"] = (extras["fs_3d_256_f32"]["value"]
+                                            / extras["fs_3d_256_f64"]["value"])
+        # adjoint cost: 2D 512^2, c + 2 eta, FP32, K = 50
+        cfg4, w4 = I.workload_config("W4")
+        u4 = I.workload_ic(cfg4, w4)
+        s4 = Solver(cfg4, "f32")
+        s4.set_fields(u4)
+        K = w4["K"]
+        ck = s4.fields.clone()
+        tf = time_fs(s4, w4["dt_fs"], K, 10, torch) / K
+        seg = s4.segment_store(K)
+        lam0 = torch.randn_like(ck)
+        lam = lam0.clone()
+        s4.adjoint_fs(w4["dt_fs"], K, ck, lam, seg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            lam.copy_(lam0)
+            s4.adjoint_fs(w4["dt_fs"], K, ck, lam, seg)
+        torch.cuda.synchronize()
+        ta = (time.perf_counter() - t0) / (reps * K)
+        extras["adjoint_2d_512_f32"] = {"forward_ms_per_step": 1e3 * tf,
+                                        "adjoint_ms_per_step_incl_recompute": 1e3 * ta,
+                                        "adjoint_over_forward": ta / tf}
+        del s4, seg, lam, ck
+        torch.cuda.empty_cache()
+        extras["paper_reference"] = {
+            "hardware": "GeForce RTX 2080 Ti (4352 CUDA cores, 11 GB), CUDA 10.1, FP64, "
+                        "PyCUDA + scikit-cuda (cuFFT)",
+            "fs_over_fd_time_per_step_per_point": {"2d": "5.2-6.5", "3d": "2.3-4.3"},
+            "fs_256sq_dt1e-3_t1_to_100_wall_s": 46,
+            "derived_fs_rate_256sq_pt_upd_per_s": 1.41e8,
+            "fd_2048sq_wall": "32 days (derived 1.01e9 pt-upd/s)"}
+        out["extras"] = extras
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(cfg, u0, dt)
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

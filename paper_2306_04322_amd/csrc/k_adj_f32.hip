@@ -1,0 +1,3 @@
+// Adjoint row-pass instantiations, single precision.
+#define PF_T float
+#include "k_adj.inc"

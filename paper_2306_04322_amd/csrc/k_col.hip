@@ -41,7 +41,8 @@ int col_launch<double>(int n, int nouter, const ColArgs<double>& a, hipStream_t 
 
 __global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ partials, int n,
                                                      int width, double* __restrict__ out,
-                                                     double s0, double s1, double s2, double s3) {
+                                                     double s0, double s1, double s2, double s3,
+                                                     int accumulate) {
   __shared__ double red[4 * 4];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
@@ -52,14 +53,14 @@ __global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ 
   block_sum<4>(acc, red);
   if (threadIdx.x == 0) {
     const double sc[4] = {s0, s1, s2, s3};
-    for (int i = 0; i < width; ++i) out[i] = acc[i] * sc[i];
+    for (int i = 0; i < width; ++i) out[i] = (accumulate ? out[i] : 0.0) + acc[i] * sc[i];
   }
 }
 
 int reduce_launch(const double* partials, int n, int width, double* out, const double* scale4,
-                  hipStream_t s) {
+                  int accumulate, hipStream_t s) {
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, partials, n, width, out, scale4[0],
-                     scale4[1], scale4[2], scale4[3]);
+                     scale4[1], scale4[2], scale4[3], accumulate);
   return 1;
 }
 

@@ -222,6 +222,135 @@ xpass_kernel(XArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint row pass.  Input: the x-spectra s_in of (a_c, b_c, a_1..a_p), i.e.
+// a_c = S_c lambda_c, b_c = Q_c lambda_c, a_i = S_eta lambda_i already
+// transformed back along the strided axes.  Per point it forms
+//   v = (dt M b_c, dt L a_1, ..., dt L a_p)
+//   lambda^n = (a_c, a_1, ..., a_p) - H_f(u^n) v
+// stores lambda^n over lambda^(n+1) in `lam`, accumulates the double dot
+// products of the parameter gradients
+//   q0 = <b_c, df/dc(u^n)>,  q1 = <lambda_c - a_c, c^(n+1)>,
+//   q2 = sum_i <a_i, df/deta_i(u^n)>,  q3 = sum_i <lambda_i - a_i, eta_i^(n+1)>
+// into partials[block][4], and optionally R2C-transforms lambda^n (the
+// first transform of the next adjoint step) into b_out.
+template <typename T>
+struct AdjArgs {
+  const c2<T>* s_in;
+  const T* u_n;
+  const T* u_np1;
+  T* lam;
+  c2<T>* b_out;
+  const c2<T>* twx;
+  double* partials;
+  long long fs_real, fs_spec;
+  int rows, Sx, F, do_fwd;
+  FeParams<T> fe;
+  T dtM, dtL;
+};
+
+template <typename T, int NX, int PMAX>
+struct AGeom {
+  static constexpr int NH = NX / 2;
+  static constexpr int E = NH < 4 ? NH : 4;
+  static constexpr int TEAM = NH / E;
+  static constexpr int ROWS = TEAM >= 64 ? 1 : 64 / TEAM;
+  static constexpr int WG = ROWS * TEAM;
+  static constexpr int REGION = NH + 1;
+};
+
+template <typename T, int NX, int PMAX>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, AGeom<T, NX, PMAX>::WG)))
+adj_row_kernel(AdjArgs<T> a) {
+  using G = AGeom<T, NX, PMAX>;
+  constexpr int E = G::E, TEAM = G::TEAM, ROWS = G::ROWS;
+  constexpr int FB = PMAX + 1;
+  __shared__ c2<T> lds[ROWS * G::REGION];
+  __shared__ double red[4 * (G::WG / 64 + 1)];
+  const int lane = threadIdx.x;
+  const int team = lane / TEAM;
+  const int t = lane - team * TEAM;
+  const int row = blockIdx.x * ROWS + team;
+  const bool active = row < a.rows;
+  const long long rrow = active ? row : 0;
+  c2<T>* my = lds + team * G::REGION;
+  const int F = a.F;
+  const int p = F - 1;
+
+  // w[0] = a_c, w[1..p] = a_i, bc = b_c; overwritten by lambda^n
+  c2<T> w[FB][E], bc[E];
+  row_c2r<T, NX, E>(w[0], a.s_in + rrow * a.Sx, active, t, my, a.twx);
+  row_c2r<T, NX, E>(bc, a.s_in + a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+#pragma unroll
+  for (int i = 0; i < PMAX; ++i)
+    if (i < p) row_c2r<T, NX, E>(w[1 + i], a.s_in + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  if (active) {
+    const long long off = rrow * NX;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int idx = 2 * (t + TEAM * m);
+      c2<T> un[FB], un1[FB], lm[FB];
+#pragma unroll
+      for (int f = 0; f < FB; ++f)
+        if (f < F) {
+          un[f] = *reinterpret_cast<const c2<T>*>(a.u_n + f * a.fs_real + off + idx);
+          un1[f] = *reinterpret_cast<const c2<T>*>(a.u_np1 + f * a.fs_real + off + idx);
+          lm[f] = *reinterpret_cast<const c2<T>*>(a.lam + f * a.fs_real + off + idx);
+        }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        T eta[PMAX], ge[PMAX], ve[PMAX], oe[PMAX];
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i) {
+          eta[i] = (i < p) ? (h ? un[1 + i].y : un[1 + i].x) : T(0);
+          const T ai = (i < p) ? (h ? w[1 + i][m].y : w[1 + i][m].x) : T(0);
+          ve[i] = a.dtL * ai;
+          ge[i] = T(0);
+          oe[i] = T(0);
+        }
+        const T c = h ? un[0].y : un[0].x;
+        const T ac = h ? w[0][m].y : w[0][m].x;
+        const T b = h ? bc[m].y : bc[m].x;
+        T gc, oc;
+        fe_grad<T, PMAX>(a.fe, p, c, eta, gc, ge);
+        fe_hvp<T, PMAX>(a.fe, p, c, eta, a.dtM * b, ve, oc, oe);
+        const T lc = h ? lm[0].y : lm[0].x;
+        const T cn1 = h ? un1[0].y : un1[0].x;
+        q[0] += double(b) * double(gc);
+        q[1] += double(lc - ac) * double(cn1);
+        const T nc = ac - oc;
+        if (h) w[0][m].y = nc; else w[0][m].x = nc;
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i)
+          if (i < p) {
+            const T ai = h ? w[1 + i][m].y : w[1 + i][m].x;
+            const T li = h ? lm[1 + i].y : lm[1 + i].x;
+            const T en1 = h ? un1[1 + i].y : un1[1 + i].x;
+            q[2] += double(ai) * double(ge[i]);
+            q[3] += double(li - ai) * double(en1);
+            const T ni = ai - oe[i];
+            if (h) w[1 + i][m].y = ni; else w[1 + i][m].x = ni;
+          }
+      }
+#pragma unroll
+      for (int f = 0; f < FB; ++f)
+        if (f < F) *reinterpret_cast<c2<T>*>(a.lam + f * a.fs_real + off + idx) = w[f][m];
+    }
+  }
+  block_sum<4>(q, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.partials[4 * blockIdx.x + k] = q[k];
+  }
+  if (a.do_fwd) {
+#pragma unroll
+    for (int f = 0; f < FB; ++f)
+      if (f < F) row_r2c<T, NX, E>(w[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Column pass.
 
 enum { COL_FWD = 0, COL_INV = 1, COL_UPDATE = 2, COL_ADJ = 3, COL_ENERGY = 4 };
@@ -397,9 +526,11 @@ struct FdArgs {
 };
 
 // Single work-group fixed-order sum of `n` records of `width` doubles:
-// out[i] = scale[i] * sum_r partials[r * width + i].
+// out[i] = scale[i] * sum_r partials[r * width + i]  (added to out[i] when
+// `accumulate` is set).
 __global__ void __launch_bounds__(256) reduce_kernel(const double* __restrict__ partials, int n,
                                                      int width, double* __restrict__ out,
-                                                     double s0, double s1, double s2, double s3);
+                                                     double s0, double s1, double s2, double s3,
+                                                     int accumulate);
 
 }  // namespace pf

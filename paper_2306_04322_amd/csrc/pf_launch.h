@@ -20,6 +20,6 @@ template <typename T> int adj_row_launch(int nx, int p, const AdjArgs<T>& a, hip
 template <typename T> int col_launch(int n, int nouter, const ColArgs<T>& a, hipStream_t s);
 template <typename T> int fd_launch(int which, int p, const FdArgs<T>& a, hipStream_t s);
 int reduce_launch(const double* partials, int n, int width, double* out, const double* scale4,
-                  hipStream_t s);
+                  int accumulate, hipStream_t s);
 
 }  // namespace pf

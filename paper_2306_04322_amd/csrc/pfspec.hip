@@ -214,10 +214,10 @@ pf_status col(pf_handle* h, ColArgs<T>& a, int axis, int* nblk) {
 }
 
 pf_status reduce(pf_handle* h, int n, int width, double* out, double s0, double s1, double s2,
-                 double s3) {
+                 double s3, int accumulate = 0) {
   const double sc[4] = {s0, s1, s2, s3};
   const int pi = prof_begin(h, PROF_RED);
-  reduce_launch(partials(h), n, width, out, sc, h->stream);
+  reduce_launch(partials(h), n, width, out, sc, accumulate, h->stream);
   prof_end(h, pi);
   return check_launch("reduction");
 }
@@ -436,6 +436,80 @@ void fill_staging(pf_handle* h) {
   }
 }
 
+// Discrete adjoint of k FS steps (see AdjArgs for the per-point algebra).
+// The segment's states are recomputed into `store` with the forward kernels,
+// then the adjoint steps run from the last step to the first:
+//   R2C of lambda -> strided transforms and the multipliers D_c, D_c k2,
+//   D_eta (column pass, adjoint mode) -> adjoint row pass.
+template <typename T>
+pf_status adjoint_run(pf_handle* h, double dt, long long k, const T* u0, T* lam, double dparams[4],
+                      T* store) {
+  PF_TRY(fs_run<T>(h, dt, k, u0, nullptr, store));
+  const long long fsz = (long long)h->F * h->P;
+  double* acc = scal(h) + SC_DPAR;
+  // first transform of lambda^k
+  XArgs<T> x = xargs<T>(h);
+  x.u_in = lam;
+  x.b_out = specB<T>(h);
+  x.flags = X_LOAD_REAL | X_FWD_RAW;
+  PF_TRY(row<T>(h, x, nullptr));
+  for (long long n = k - 1; n >= 0; --n) {
+    ColArgs<T> a = cargs<T>(h, dt);
+    a.src = specB<T>(h);
+    if (h->nd == 2) {
+      a.dst = specS<T>(h);
+      a.mode = COL_ADJ;
+      PF_TRY(col<T>(h, a, 1, nullptr));
+    } else {
+      a.dst = specB<T>(h);
+      a.mode = COL_FWD;
+      PF_TRY(col<T>(h, a, 1, nullptr));
+      a.dst = specS<T>(h);
+      a.mode = COL_ADJ;
+      PF_TRY(col<T>(h, a, 2, nullptr));
+      a.src = specS<T>(h);
+      a.mode = COL_INV;
+      a.F = h->F + 1;
+      PF_TRY(col<T>(h, a, 1, nullptr));
+    }
+    AdjArgs<T> r;
+    std::memset(&r, 0, sizeof(r));
+    r.s_in = specS<T>(h);
+    r.u_n = (n == 0) ? u0 : store + (n - 1) * fsz;
+    r.u_np1 = store + n * fsz;
+    r.lam = lam;
+    r.b_out = specB<T>(h);
+    r.twx = twp<T>(h, 0);
+    r.partials = partials(h);
+    r.fs_real = h->P;
+    r.fs_spec = (long long)h->spec_field;
+    r.rows = h->rows;
+    r.Sx = h->Sx;
+    r.F = h->F;
+    r.do_fwd = n > 0 ? 1 : 0;
+    r.fe = fe_params<T>(h);
+    r.dtM = T(dt * h->M);
+    r.dtL = T(dt * h->L);
+    const int pi = prof_begin(h, PROF_ADJ);
+    const int nb = adj_row_launch<T>(h->nx, h->p, r, h->stream);
+    prof_end(h, pi);
+    if (nb < 0) return fail(PF_ERR_UNSUPPORTED, "adjoint row pass: unsupported Nx");
+    PF_TRY(check_launch("adjoint row pass"));
+    PF_TRY(reduce(h, nb, 4, acc, 1, 1, 1, 1, n == k - 1 ? 0 : 1));
+  }
+  double q[4];
+  if (hipMemcpyAsync(q, acc, sizeof(q), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return fail(PF_ERR_HIP, std::string("adjoint readback: ") + hipGetErrorString(hipGetLastError()));
+  dparams[0] += -dt * q[0] - q[1] / h->M;
+  dparams[1] += -q[1] / h->kc;
+  dparams[2] += -dt * q[2] - q[3] / h->L;
+  dparams[3] += -q[3] / h->ke;
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(dparams[i])) return fail(PF_ERR_NONFINITE, "parameter gradient is not finite");
+  return PF_OK;
+}
+
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 }  // namespace
@@ -604,9 +678,16 @@ pf_status pf_energy(pf_handle* h, int32_t scheme, double out[5]) {
 
 pf_status pf_adjoint_fs(pf_handle* h, double dt, int64_t k, const void* u_ckpt, void* lambda,
                         double dparams[4], void* seg_store) {
-  (void)dt; (void)k; (void)u_ckpt; (void)lambda; (void)dparams; (void)seg_store;
-  if (!h) return fail(PF_ERR_INVALID, "handle is NULL");
-  return fail(PF_ERR_UNSUPPORTED, "adjoint not built yet");
+  PF_TRY(check_step(h, dt, k));
+  if (!u_ckpt || !lambda || !dparams || (k > 0 && !seg_store))
+    return fail(PF_ERR_INVALID, "u_ckpt, lambda, dparams and seg_store must be non-NULL");
+  if (k == 0) return PF_OK;
+  return h->es == 4 ? adjoint_run<float>(h, dt, k, static_cast<const float*>(u_ckpt),
+                                         static_cast<float*>(lambda), dparams,
+                                         static_cast<float*>(seg_store))
+                    : adjoint_run<double>(h, dt, k, static_cast<const double*>(u_ckpt),
+                                          static_cast<double*>(lambda), dparams,
+                                          static_cast<double*>(seg_store));
 }
 
 pf_status pf_profile_enable(pf_handle* h, int32_t enable) {

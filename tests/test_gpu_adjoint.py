@@ -1,0 +1,163 @@
+"""GPU discrete adjoint (pf_adjoint_fs) and the autograd wrapper.
+
+Checked against the oracle's CPU adjoint on small grids, against central
+finite differences of the GPU forward at the differentiable-benchmark size
+(2D 512^2, c + 2 eta, 500 steps, checkpoints every 50), and for the
+bit-exact recomputation of the forward trajectory."""
+
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj
+from oracle import fs as ofs
+from paper_2306_04322_amd import inputs as I
+from parity_util import announce, fp32_rounded, gpu_or_fail
+
+pytestmark = pytest.mark.gpu
+
+
+def _cfg(ndim, n, p, fe=None, **kin):
+    base = dict(M=4.0, kappa_c=2.0, L=3.0, kappa_eta=1.5)
+    base.update(kin)
+    return I.make_config(ndim, n, 1.0, p, fe or I.PAPER_FE, **base)
+
+
+def _gpu_adjoint(cfg, prec, u0, lam_T, dt, nsteps, K):
+    torch = gpu_or_fail()
+    from paper_2306_04322_amd.pfspec import Solver
+    s = Solver(cfg, prec)
+    dtype = s.dtype
+    s.set_fields(u0)
+    ckpts, lens = [], []
+    done = 0
+    while done < nsteps:
+        k = min(K, nsteps - done)
+        ckpts.append(s.fields.clone())
+        lens.append(k)
+        s.step_fs(dt, k)
+        done += k
+    uT = s.get_fields()
+    lam = torch.as_tensor(lam_T(uT)).to(s.device, dtype).contiguous()
+    seg = s.segment_store(K)
+    dpar = np.zeros(4)
+    for ck, k in zip(reversed(ckpts), reversed(lens)):
+        dpar = s.adjoint_fs(dt, k, ck, lam, seg, dpar)
+    torch.cuda.synchronize()
+    return lam.double().cpu().numpy(), dpar, uT
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["paper2d", "poly2d", "paper3d", "fd2"])
+def test_adjoint_matches_oracle(case, prec):
+    if case == "paper2d":
+        cfg = _cfg(2, 32, 2)
+    elif case == "poly2d":
+        cfg = _cfg(2, (16, 32), 3, I.POLY_FE)
+    elif case == "paper3d":
+        cfg = _cfg(3, (16, 8, 8), 4)
+    else:
+        cfg = _cfg(2, (32, 16), 2, kmode="fd2")
+    dt, nsteps, K = (0.02, 10, 4) if case != "poly2d" else (1e-3, 10, 4)
+    u0 = I.random_ic(cfg, 12)
+    if prec == "f32":
+        u0 = fp32_rounded(u0)
+    w = I.random_direction(cfg, 13)
+    announce("adjoint vs oracle", case, prec)
+    lam0, dpar, uT = _gpu_adjoint(cfg, prec, u0, lambda uT: w, dt, nsteps, K)
+    traj = oadj.trajectory(u0, cfg, dt, nsteps)
+    rlam, rpar = oadj.fs_adjoint(traj, w, cfg, dt)
+    err = np.linalg.norm(lam0 - rlam) / np.linalg.norm(rlam)
+    perr = np.max(np.abs(dpar - rpar) / np.maximum(np.abs(rpar), 1e-12 * np.max(np.abs(rpar))))
+    print(case, prec, "lambda rel-L2", err, "param rel", perr, dpar, rpar)
+    if prec == "f64":
+        assert err <= 1e-10 and perr <= 1e-9
+    else:
+        assert err <= 1e-4 and perr <= 1e-3
+
+
+def test_recompute_is_bit_exact():
+    torch = gpu_or_fail()
+    from paper_2306_04322_amd.pfspec import Solver
+    cfg = _cfg(2, 64, 2)
+    u0 = I.random_ic(cfg, 14)
+    announce("adjoint recompute bit-exact")
+    s = Solver(cfg, "f32")
+    s.set_fields(u0)
+    ck = s.fields.clone()
+    s.step_fs(0.1, 7)
+    fwd = s.fields.clone()
+    seg = s.segment_store(7)
+    lam = torch.zeros_like(ck)
+    s.adjoint_fs(0.1, 7, ck, lam, seg)
+    last = seg.view(7, *s.shape)[6]
+    assert bool((last == fwd).all())
+    # the bound fields are untouched by the adjoint
+    assert bool((s.fields == fwd).all())
+
+
+def _loss_and_grads(prec, params, u0, target, solver_cache):
+    import torch
+    from paper_2306_04322_amd.autograd import fs_rollout
+    s = solver_cache[prec]
+    u = torch.as_tensor(u0, device="cuda", dtype=s.dtype).requires_grad_(True)
+    pt = torch.tensor(params, dtype=torch.float64, requires_grad=True)
+    uT = fs_rollout(u, pt, s, 0.1, 500, 50)
+    loss = torch.mean((uT[0].double() - target) ** 2)
+    loss.backward()
+    return float(loss), u.grad.double().cpu().numpy(), pt.grad.numpy()
+
+
+def test_differentiable_512_against_central_differences():
+    """2D 512^2, c + 2 eta, dt 0.1 x 500 steps, checkpoints every 50; loss
+    mean((c_T - c_target)^2) with c_target from the same seed run at M = 4,
+    kappa_c = 2.5.  FP64 adjoint vs central differences (h = 1e-3) of the
+    FP64 forward; FP32 adjoint vs FP64 adjoint."""
+    torch = gpu_or_fail()
+    from paper_2306_04322_amd.pfspec import Solver
+    cfg, w = I.workload_config("W4")
+    u0 = I.workload_ic(cfg, w)
+    base = [5.0, 3.0, 5.0, 3.0]
+    announce("differentiable 512^2 target run")
+    s64 = Solver(cfg, "f64")
+    s64.set_params(4.0, 2.5, 5.0, 3.0)
+    s64.set_fields(u0)
+    s64.step_fs(0.1, 500)
+    target = s64.fields[0].clone()
+    cache = {"f64": s64, "f32": Solver(cfg, "f32")}
+    announce("differentiable 512^2 adjoint f64")
+    J, gu, gp = _loss_and_grads("f64", base, u0, target, cache)
+    assert J > 0
+    h = 1e-3
+    for i in range(4):
+        pp = list(base)
+        pm = list(base)
+        pp[i] += h
+        pm[i] -= h
+        with torch.no_grad():
+            Jp = _loss_only(s64, pp, u0, target)
+            Jm = _loss_only(s64, pm, u0, target)
+        num = (Jp - Jm) / (2 * h)
+        print("param", i, "adjoint", gp[i], "central FD", num)
+        assert abs(gp[i] - num) <= 2e-4 * abs(num) + 1e-14
+    v = I.random_direction(cfg, 77, 1.0)
+    hu = 1e-3
+    with torch.no_grad():
+        Jp = _loss_only(s64, base, u0 + hu * v, target)
+        Jm = _loss_only(s64, base, u0 - hu * v, target)
+    num = (Jp - Jm) / (2 * hu)
+    dirv = float(np.sum(gu * v))
+    print("direction: adjoint", dirv, "central FD", num)
+    assert abs(dirv - num) <= 2e-4 * abs(num)
+    announce("differentiable 512^2 adjoint f32")
+    J32, gu32, gp32 = _loss_and_grads("f32", base, fp32_rounded(u0), target.float().double(), cache)
+    print("f32 params", gp32, "f64 params", gp)
+    assert np.max(np.abs(gp32 - gp) / np.abs(gp)) <= 1e-2
+    assert np.linalg.norm(gu32 - gu) / np.linalg.norm(gu) <= 1e-2
+
+
+def _loss_only(s, params, u0, target):
+    import torch
+    s.set_params(*params)
+    s.set_fields(u0)
+    s.step_fs(0.1, 500)
+    return float(torch.mean((s.fields[0].double() - target) ** 2))

@@ -222,17 +222,22 @@ xpass_kernel(XArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint row pass.  Input: the x-spectra s_in of (a_c, b_c, a_1..a_p), i.e.
-// a_c = S_c lambda_c, b_c = Q_c lambda_c, a_i = S_eta lambda_i already
-// transformed back along the strided axes.  Per point it forms
-//   v = (dt M b_c, dt L a_1, ..., dt L a_p)
+// Adjoint row pass.  Input: the x-spectra s_in of (e_c, b_c, e_1..e_p),
+// already transformed back along the strided axes, where
+//   e_c = (I - S_c) lambda_c,  b_c = Q_c lambda_c,  e_i = (I - S_eta) lambda_i
+// (the column pass forms e from k-space as x/(1+x) lambda^ with
+// x = dt M kappa_c |xi|^4 or dt L kappa_eta |xi|^2, so a smooth lambda does
+// not lose its digits to the subtraction lambda - S lambda).  Per point:
+//   a = lambda^(n+1) - e,  v = (dt M b_c, dt L a_1, ..., dt L a_p)
 //   lambda^n = (a_c, a_1, ..., a_p) - H_f(u^n) v
-// stores lambda^n over lambda^(n+1) in `lam`, accumulates the double dot
-// products of the parameter gradients
-//   q0 = <b_c, df/dc(u^n)>,  q1 = <lambda_c - a_c, c^(n+1)>,
-//   q2 = sum_i <a_i, df/deta_i(u^n)>,  q3 = sum_i <lambda_i - a_i, eta_i^(n+1)>
-// into partials[block][4], and optionally R2C-transforms lambda^n (the
-// first transform of the next adjoint step) into b_out.
+// stored over lambda^(n+1) in `lam`; the double dot products of the
+// parameter gradients
+//   q0 = <b_c, df/dc(u^n)>,  q1 = <e_c, c^(n+1) - mean(c)>,
+//   q2 = sum_i <a_i, df/deta_i(u^n)>,  q3 = sum_i <e_i, eta_i^(n+1)>
+// go to partials[block][4] (e_c has zero mean, so removing the held mean of
+// c changes nothing in exact arithmetic and keeps the sum well conditioned);
+// optionally lambda^n is R2C-transformed (the first transform of the next
+// adjoint step) into b_out.
 template <typename T>
 struct AdjArgs {
   const c2<T>* s_in;
@@ -241,6 +246,7 @@ struct AdjArgs {
   T* lam;
   c2<T>* b_out;
   const c2<T>* twx;
+  const double* mean_c;
   double* partials;
   long long fs_real, fs_spec;
   int rows, Sx, F, do_fwd;
@@ -276,7 +282,7 @@ adj_row_kernel(AdjArgs<T> a) {
   const int F = a.F;
   const int p = F - 1;
 
-  // w[0] = a_c, w[1..p] = a_i, bc = b_c; overwritten by lambda^n
+  // w[0] = e_c, w[1..p] = e_i, bc = b_c; w is overwritten by lambda^n
   c2<T> w[FB][E], bc[E];
   row_c2r<T, NX, E>(w[0], a.s_in + rrow * a.Sx, active, t, my, a.twx);
   row_c2r<T, NX, E>(bc, a.s_in + a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
@@ -285,6 +291,7 @@ adj_row_kernel(AdjArgs<T> a) {
     if (i < p) row_c2r<T, NX, E>(w[1 + i], a.s_in + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
 
   double q[4] = {0.0, 0.0, 0.0, 0.0};
+  const double cmean = *a.mean_c;
   if (active) {
     const long long off = rrow * NX;
 #pragma unroll
@@ -300,36 +307,38 @@ adj_row_kernel(AdjArgs<T> a) {
         }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        T eta[PMAX], ge[PMAX], ve[PMAX], oe[PMAX];
+        T eta[PMAX], ge[PMAX], ve[PMAX], oe[PMAX], ai[PMAX];
 #pragma unroll
         for (int i = 0; i < PMAX; ++i) {
           eta[i] = (i < p) ? (h ? un[1 + i].y : un[1 + i].x) : T(0);
-          const T ai = (i < p) ? (h ? w[1 + i][m].y : w[1 + i][m].x) : T(0);
-          ve[i] = a.dtL * ai;
+          const T li = (i < p) ? (h ? lm[1 + i].y : lm[1 + i].x) : T(0);
+          const T ei = (i < p) ? (h ? w[1 + i][m].y : w[1 + i][m].x) : T(0);
+          ai[i] = li - ei;
+          ve[i] = a.dtL * ai[i];
           ge[i] = T(0);
           oe[i] = T(0);
         }
         const T c = h ? un[0].y : un[0].x;
-        const T ac = h ? w[0][m].y : w[0][m].x;
+        const T ec = h ? w[0][m].y : w[0][m].x;
+        const T lc = h ? lm[0].y : lm[0].x;
+        const T ac = lc - ec;
         const T b = h ? bc[m].y : bc[m].x;
         T gc, oc;
         fe_grad<T, PMAX>(a.fe, p, c, eta, gc, ge);
         fe_hvp<T, PMAX>(a.fe, p, c, eta, a.dtM * b, ve, oc, oe);
-        const T lc = h ? lm[0].y : lm[0].x;
         const T cn1 = h ? un1[0].y : un1[0].x;
         q[0] += double(b) * double(gc);
-        q[1] += double(lc - ac) * double(cn1);
+        q[1] += double(ec) * (double(cn1) - cmean);
         const T nc = ac - oc;
         if (h) w[0][m].y = nc; else w[0][m].x = nc;
 #pragma unroll
         for (int i = 0; i < PMAX; ++i)
           if (i < p) {
-            const T ai = h ? w[1 + i][m].y : w[1 + i][m].x;
-            const T li = h ? lm[1 + i].y : lm[1 + i].x;
+            const T ei = h ? w[1 + i][m].y : w[1 + i][m].x;
             const T en1 = h ? un1[1 + i].y : un1[1 + i].x;
-            q[2] += double(ai) * double(ge[i]);
-            q[3] += double(li - ai) * double(en1);
-            const T ni = ai - oe[i];
+            q[2] += double(ai[i]) * double(ge[i]);
+            q[3] += double(ei) * double(en1);
+            const T ni = ai[i] - oe[i];
             if (h) w[1 + i][m].y = ni; else w[1 + i][m].x = ni;
           }
       }
@@ -459,16 +468,18 @@ col_kernel(ColArgs<T> a) {
       store(a.dst + f * a.fs_dst, v);
     }
   } else if (a.mode == COL_ADJ) {
-    // lambda^ -> a_c = D_c lambda_c^, b_c = D_c k2 lambda_c^, a_i = D_eta lambda_i^
+    // lambda^ -> e_c = x/(1+x) lambda_c^ (x = dt M kappa_c k2^2), b_c = D_c k2 lambda_c^,
+    //            e_i = y/(1+y) lambda_i^ (y = dt L kappa_eta k2)
     c2<T> b[E];
     load(a.src, v);
     team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const T k2 = kc + a.kaxis[t + TEAM * m];
-      const T D = a.invP / (T(1) + a.dtMkc * k2 * k2);
-      v[m] = mk<T>(v[m].x * D, v[m].y * D);
-      b[m] = mk<T>(v[m].x * k2, v[m].y * k2);
+      const T x = a.dtMkc * k2 * k2;
+      const T D = a.invP / (T(1) + x);
+      b[m] = mk<T>(v[m].x * D * k2, v[m].y * D * k2);
+      v[m] = mk<T>(v[m].x * D * x, v[m].y * D * x);
     }
     team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
     store(a.dst, v);
@@ -480,7 +491,8 @@ col_kernel(ColArgs<T> a) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
-        const T D = a.invP / (T(1) + a.dtLke * k2);
+        const T y = a.dtLke * k2;
+        const T D = a.invP * y / (T(1) + y);
         v[m] = mk<T>(v[m].x * D, v[m].y * D);
       }
       team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);

@@ -437,6 +437,9 @@ void fill_staging(pf_handle* h) {
 }
 
 // Discrete adjoint of k FS steps (see AdjArgs for the per-point algebra).
+// With e = (I - S) lambda the parameter-gradient increments of one step are
+//   dJ/dM += -dt q0 - q1 / M,  dJ/dkappa_c += -q1 / kappa_c,
+//   dJ/dL += -dt q2 - q3 / L,  dJ/dkappa_eta += -q3 / kappa_eta.
 // The segment's states are recomputed into `store` with the forward kernels,
 // then the adjoint steps run from the last step to the first:
 //   R2C of lambda -> strided transforms and the multipliers D_c, D_c k2,
@@ -480,6 +483,7 @@ pf_status adjoint_run(pf_handle* h, double dt, long long k, const T* u0, T* lam,
     r.lam = lam;
     r.b_out = specB<T>(h);
     r.twx = twp<T>(h, 0);
+    r.mean_c = scal(h) + SC_MEANC;
     r.partials = partials(h);
     r.fs_real = h->P;
     r.fs_spec = (long long)h->spec_field;

@@ -104,7 +104,7 @@ def _loss_and_grads(prec, params, u0, target, solver_cache):
     uT = fs_rollout(u, pt, s, 0.1, 500, 50)
     loss = torch.mean((uT[0].double() - target) ** 2)
     loss.backward()
-    return float(loss), u.grad.double().cpu().numpy(), pt.grad.numpy()
+    return float(loss.detach()), u.grad.double().cpu().numpy(), pt.grad.numpy()
 
 
 def test_differentiable_512_against_central_differences():

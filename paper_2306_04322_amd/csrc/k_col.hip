@@ -5,12 +5,18 @@
 
 namespace pf {
 
+// Returns the number of logical work items (= partial-sum records written
+// in energy mode).
 template <typename T, int N>
 static int claunch(int nouter, const ColArgs<T>& a, hipStream_t s) {
   using G = ColGeom<T, N>;
   const int tiles = (a.ncols + G::C - 1) / G::C;
-  hipLaunchKernelGGL((col_kernel<T, N>), dim3(tiles, nouter), dim3(G::WG), 0, s, a);
-  return tiles * nouter;
+  const int ngroups = a.F;
+  const long long W = (long long)tiles * nouter * ngroups;
+  const int nslots = int((W + 7) / 8);
+  hipLaunchKernelGGL((col_kernel<T, N>), dim3(8 * nslots), dim3(G::WG), 0, s, a, tiles, nouter,
+                     ngroups, nslots);
+  return int(W);
 }
 
 template <typename T>

@@ -16,8 +16,10 @@
 // input index), so an N = E^P transform needs P - 1 LDS exchanges.
 //
 // Twiddles come from a per-axis table W[q] = exp(-2 pi i q / Naxis) that the
-// host computes in double precision (rounded once for float); a length-N
-// transform on an axis of length Naxis reads W[q * (Naxis / N)].
+// host computes in extended precision (rounded once for float or double); a
+// length-N transform on an axis of length Naxis reads W[q * (Naxis / N)].
+// Each lane loads the few twiddles its passes need into registers once per
+// kernel, so no table load sits in the dependency chain of a pass.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -58,7 +60,7 @@ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
 // Multiply by exp(-2 pi i K / R) (forward) or exp(+2 pi i K / R) (inverse)
 // for R <= 16, 0 <= K < R/2.  Exact sixteenth roots of unity: cos(pi/8),
-// sin(pi/8) and sqrt(1/2) to 21 digits.
+// sin(pi/8) and sqrt(1/2) to 23 digits.
 template <int R, int K, bool INV, typename T>
 __device__ __forceinline__ c2<T> rot(c2<T> a) {
   constexpr int k16 = K * (16 / R);
@@ -128,11 +130,40 @@ constexpr int first_radix() {
   return (ilog2(N) % ilog2(E)) ? (1 << (ilog2(N) % ilog2(E))) : E;
 }
 
+// Number of passes of a length-N transform with E elements per lane: an
+// optional first pass of radix first_radix<N, E>() < E, then radix-E passes.
+template <int N, int E>
+constexpr int num_passes() {
+  return ilog2(N) / ilog2(E) + ((ilog2(N) % ilog2(E)) ? 1 : 0);
+}
+
+// Per-lane twiddles of one team transform, loaded once and reused by every
+// transform of that length the lane performs (the inverse uses their
+// conjugates).  Pass p >= 1 has radix E, one butterfly per lane (j = t), and
+// needs exp(-2 pi i r k / (NS_p E)) for r = 1..E-1, k = t mod NS_p.
+template <typename T, int N, int E>
+struct Twiddles {
+  static constexpr int P = num_passes<N, E>();
+  static constexpr int NT = (P - 1) * (E - 1) > 0 ? (P - 1) * (E - 1) : 1;
+  c2<T> w[NT];
+  __device__ __forceinline__ void load(int t, const c2<T>* __restrict__ tw, int tws) {
+    int ns = first_radix<N, E>();
+#pragma unroll
+    for (int p = 1; p < P; ++p) {
+      const int k = t & (ns - 1);
+      const int step = N / (ns * E);
+#pragma unroll
+      for (int r = 1; r < E; ++r) w[(p - 1) * (E - 1) + (r - 1)] = tw[(r * k * step) * tws];
+      ns *= E;
+    }
+  }
+};
+
 // One Stockham pass.  `lds` points at element 0 of this team's exchange
-// area; element i lives at lds[i * LS].
+// area; element i lives at lds[i * LS].  `tw` holds this pass's twiddles
+// (radix-E passes after the first only).
 template <typename T, int N, int E, int R, int NS, bool INV, bool LAST, int LS>
-__device__ __forceinline__ void stockham_pass(c2<T>* v, int t, c2<T>* lds,
-                                              const c2<T>* __restrict__ tw, int tws) {
+__device__ __forceinline__ void stockham_pass(c2<T>* v, int t, c2<T>* lds, const c2<T>* tw) {
   constexpr int TEAM = N / E;
   constexpr int BPL = E / R;  // butterflies per lane
 #pragma unroll
@@ -143,11 +174,9 @@ __device__ __forceinline__ void stockham_pass(c2<T>* v, int t, c2<T>* lds,
 #pragma unroll
     for (int r = 0; r < R; ++r) x[r] = v[b + r * BPL];
     if constexpr (NS > 1) {
+      static_assert(R == E && BPL == 1, "twiddled passes are radix E");
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        c2<T> w = tw[(r * k * (N / (NS * R))) * tws];
-        x[r] = INV ? cmulc<T>(x[r], w) : cmul<T>(x[r], w);
-      }
+      for (int r = 1; r < R; ++r) x[r] = INV ? cmulc<T>(x[r], tw[r - 1]) : cmul<T>(x[r], tw[r - 1]);
     }
     Dft<T, R, INV>::run(x);
     if constexpr (LAST) {
@@ -161,31 +190,48 @@ __device__ __forceinline__ void stockham_pass(c2<T>* v, int t, c2<T>* lds,
   }
 }
 
-template <typename T, int N, int E, bool INV, int NS, int LS>
+// Exchange synchronisation.  A team that fits in one wavefront only needs
+// its own LDS traffic ordered: LDS operations of one wavefront execute in
+// issue order, so a compiler fence at wavefront scope (which also keeps the
+// compiler from moving one lane's accesses across another lane's) is
+// enough.  Larger teams synchronise the whole work-group.
+template <bool WAVE>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
+template <typename T, int N, int E, bool INV, int NS, int LS, bool WAVE, int PI>
 struct FftPasses {
   static constexpr int R = (NS == 1) ? first_radix<N, E>() : E;
   static constexpr bool LAST = (NS * R == N);
-  __device__ __forceinline__ static void run(c2<T>* v, int t, c2<T>* lds,
-                                             const c2<T>* __restrict__ tw, int tws) {
-    stockham_pass<T, N, E, R, NS, INV, LAST, LS>(v, t, lds, tw, tws);
+  __device__ __forceinline__ static void run(c2<T>* v, int t, c2<T>* lds, const c2<T>* twr) {
+    stockham_pass<T, N, E, R, NS, INV, LAST, LS>(v, t, lds, twr + (PI > 0 ? (PI - 1) * (E - 1) : 0));
     if constexpr (!LAST) {
       constexpr int TEAM = N / E;
-      __syncthreads();
+      team_sync<WAVE>();
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = lds[(t + TEAM * m) * LS];
-      __syncthreads();
-      FftPasses<T, N, E, INV, NS * R, LS>::run(v, t, lds, tw, tws);
+      team_sync<WAVE>();
+      FftPasses<T, N, E, INV, NS * R, LS, WAVE, PI + 1>::run(v, t, lds, twr);
     }
   }
 };
 
-// Length-N complex FFT by a team; unnormalised in both directions.
-// Every lane of the work-group must call this (it contains barriers).
-template <typename T, int N, int E, bool INV, int LS>
-__device__ __forceinline__ void team_fft(c2<T>* v, int t, c2<T>* lds,
-                                         const c2<T>* __restrict__ tw, int tws) {
+// Length-N complex FFT by a team; unnormalised in both directions.  `tw`
+// holds the lane's twiddles (Twiddles<T, N, E>::load).  With WAVE = false
+// every lane of the work-group must call this (it contains work-group
+// barriers); with WAVE = true the team must lie within one wavefront and
+// only that team's lanes take part.
+template <typename T, int N, int E, bool INV, int LS, bool WAVE = false>
+__device__ __forceinline__ void team_fft(c2<T>* v, int t, c2<T>* lds, const Twiddles<T, N, E>& tw) {
   static_assert(N >= E && E >= 2 && (N % E) == 0, "bad FFT team shape");
-  FftPasses<T, N, E, INV, 1, LS>::run(v, t, lds, tw, tws);
+  static_assert(!WAVE || N / E <= 64, "a wave-synchronised team must fit one wavefront");
+  FftPasses<T, N, E, INV, 1, LS, WAVE, 0>::run(v, t, lds, tw.w);
 }
 
 }  // namespace pf

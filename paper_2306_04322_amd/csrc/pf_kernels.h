@@ -69,7 +69,8 @@ struct XGeom {
 // extension (x_j = sum_k X_k exp(+2 pi i j k / NX)).
 template <typename T, int NX, int E>
 __device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src, bool active,
-                                        int t, c2<T>* my, const c2<T>* __restrict__ twx) {
+                                        int t, c2<T>* my, const c2<T>* __restrict__ twx,
+                                        const Twiddles<T, NX / 2, E>& tws) {
   constexpr int NH = NX / 2;
   constexpr int TEAM = NH / E;
   c2<T> X[E];
@@ -88,16 +89,17 @@ __device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src,
     v[m] = mk<T>(s.x - d.y, s.y + d.x);                 // s + i d
   }
   __syncthreads();
-  team_fft<T, NH, E, true, 1>(v, t, my, twx, 2);
+  team_fft<T, NH, E, true, 1>(v, t, my, tws);
 }
 
 // R2C of one row held as v[m] = (x[2k], x[2k+1]); writes X[0..NH] to dst.
 template <typename T, int NX, int E>
 __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* __restrict__ dst, bool active, int t,
-                                        c2<T>* my, const c2<T>* __restrict__ twx) {
+                                        c2<T>* my, const c2<T>* __restrict__ twx,
+                                        const Twiddles<T, NX / 2, E>& tws) {
   constexpr int NH = NX / 2;
   constexpr int TEAM = NH / E;
-  team_fft<T, NH, E, false, 1>(v, t, my, twx, 2);
+  team_fft<T, NH, E, false, 1>(v, t, my, tws);
 #pragma unroll
   for (int m = 0; m < E; ++m) my[t + TEAM * m] = v[m];
   __syncthreads();
@@ -133,6 +135,8 @@ xpass_kernel(XArgs<T> a) {
   c2<T>* my = lds + team * G::REGION;
   const int F = a.F;
   const int p = F - 1;
+  Twiddles<T, NH, E> tws;
+  tws.load(t, a.twx, 2);
 
   c2<T> u[FB][E];
   if (a.flags & X_LOAD_REAL) {
@@ -146,7 +150,7 @@ xpass_kernel(XArgs<T> a) {
   } else {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
-      if (f < F) row_c2r<T, NX, E>(u[f], a.s_in + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+      if (f < F) row_c2r<T, NX, E>(u[f], a.s_in + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
   }
 
   if ((a.flags & X_STORE_REAL) && active) {
@@ -209,15 +213,190 @@ xpass_kernel(XArgs<T> a) {
       }
       gcv[m] = mk<T>(gcx, gcy);
     }
-    row_r2c<T, NX, E>(u[0], a.b_out + 0 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
-    row_r2c<T, NX, E>(gcv, a.b_out + 1 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+    row_r2c<T, NX, E>(u[0], a.b_out + 0 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
+    row_r2c<T, NX, E>(gcv, a.b_out + 1 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
 #pragma unroll
     for (int i = 0; i < PMAX; ++i)
-      if (i < p) row_r2c<T, NX, E>(u[1 + i], a.b_out + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+      if (i < p) row_r2c<T, NX, E>(u[1 + i], a.b_out + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
   } else if (a.flags & X_FWD_RAW) {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
-      if (f < F) row_r2c<T, NX, E>(u[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+      if (f < F) row_r2c<T, NX, E>(u[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass, one wavefront per transform.  The work-group owns ROWS rows and
+// stages them in an LDS row buffer of F + 1 real rows each (slot 0 = c,
+// slot 1 = df/dc, slot 2 + i = eta_i, so the right-hand sides overwrite
+// their inputs in place).  Phase 1: each wavefront inverse-transforms (C2R)
+// one (row, field) x-spectrum, using that field's slot as its FFT exchange
+// area, and leaves the real row in the slot.  Phase 2: all lanes evaluate
+// the pointwise part (real-row store, double sums, derivative) on the row
+// buffer.  Phase 3: each wavefront forward-transforms (R2C) one (row,
+// output) slot and stores its x-spectrum.  FFT exchanges inside a phase are
+// wavefront-local, so only the two phase boundaries synchronise the
+// work-group.  Used when a transform fits one wavefront (Nx <= 2048) and
+// the row buffer fits LDS; otherwise xpass_kernel above.
+template <typename T, int NX, int PMAX>
+struct RGeom {
+  static constexpr int NH = NX / 2;
+  static constexpr int E = NH >= 512 ? (NH / 64 < 16 ? NH / 64 : 16) : (NH < 8 ? NH : 8);
+  static constexpr int TEAM = NH / E;
+  static constexpr bool WAVE_OK = TEAM <= 64;
+  static constexpr int UPW = WAVE_OK ? 64 / TEAM : 1;  // transforms per wavefront
+  static constexpr int ROWS = NX >= 1024 ? 1 : 1024 / NX;
+  static constexpr int NW = 4;
+  static constexpr int WG = 64 * NW;
+  static constexpr int SLOTS = PMAX + 2;
+  static constexpr long LDS_BYTES = long(ROWS) * SLOTS * NX * long(sizeof(T));
+  static constexpr bool FITS = WAVE_OK && LDS_BYTES <= 96 * 1024;
+};
+
+template <typename T, int NX, int PMAX>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, RGeom<T, NX, PMAX>::WG)))
+rowpass_kernel(XArgs<T> a) {
+  using G = RGeom<T, NX, PMAX>;
+  constexpr int NH = G::NH, E = G::E, TEAM = G::TEAM, UPW = G::UPW, ROWS = G::ROWS;
+  constexpr int NW = G::NW, SL = G::SLOTS, WG = G::WG;
+  static_assert(G::FITS, "row pass v2 does not fit this size");
+  __shared__ __align__(16) T rb[ROWS * SL * NX];
+  __shared__ double red[2 * (NW + 1)];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int unit = lane / TEAM;
+  const int t = lane - unit * TEAM;
+  const int row0 = blockIdx.x * ROWS;
+  const int F = a.F;
+  const int p = F - 1;
+  Twiddles<T, NH, E> tws;
+  tws.load(t, a.twx, 2);
+
+  // phase 1: real rows into the row buffer
+  if (a.flags & X_LOAD_REAL) {
+    const int n2 = ROWS * F * NH;
+    for (int q = tid; q < n2; q += WG) {
+      const int x2 = q % NH;
+      const int rf = q / NH;
+      const int f = rf % F;
+      const int r = rf / F;
+      const int row = row0 + r;
+      if (row < a.rows) {
+        const c2<T>* src = reinterpret_cast<const c2<T>*>(a.u_in + f * a.fs_real + (long long)row * NX);
+        c2<T>* ar = reinterpret_cast<c2<T>*>(rb + (r * SL + (f == 0 ? 0 : f + 1)) * NX);
+        ar[x2] = src[x2];
+      }
+    }
+  } else {
+    const int njobs = ROWS * F;
+    for (int base = wave * UPW; base < njobs; base += NW * UPW) {
+      const int j = base + unit;
+      const int r = j / F;
+      const int f = j - r * F;
+      if (j < njobs && row0 + r < a.rows) {
+        const c2<T>* src = a.s_in + f * a.fs_spec + (long long)(row0 + r) * a.Sx;
+        c2<T>* ar = reinterpret_cast<c2<T>*>(rb + (r * SL + (f == 0 ? 0 : f + 1)) * NX);
+        c2<T> v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int k = t + TEAM * m;
+          const c2<T> X = src[k];
+          const c2<T> Y = conj<T>(src[NH - k]);
+          const c2<T> sm = add<T>(X, Y);
+          const c2<T> d = cmulc<T>(sub<T>(X, Y), a.twx[k]);  // * exp(+2 pi i k / NX)
+          v[m] = mk<T>(sm.x - d.y, sm.y + d.x);
+        }
+        team_fft<T, NH, E, true, 1, true>(v, t, ar, tws);
+        team_sync<true>();
+#pragma unroll
+        for (int m = 0; m < E; ++m) ar[t + TEAM * m] = v[m];
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 2: pointwise work on the row buffer
+  double acc[2] = {0.0, 0.0};
+  const int npts = ROWS * NX;
+  for (int q = tid; q < npts; q += WG) {
+    const int r = q / NX;
+    const int x = q - r * NX;
+    const int row = row0 + r;
+    if (row < a.rows) {
+      T* pt = rb + r * SL * NX + x;
+      const T c = pt[0];
+      T eta[PMAX];
+#pragma unroll
+      for (int i = 0; i < PMAX; ++i) eta[i] = (i < p) ? pt[(2 + i) * NX] : T(0);
+      if (a.flags & X_STORE_REAL) {
+        const long long off = (long long)row * NX + x;
+        a.u_out[off] = c;
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i)
+          if (i < p) a.u_out[(1 + i) * a.fs_real + off] = eta[i];
+      }
+      if (a.flags & X_ESUM) {
+        acc[0] += fe_density<T, PMAX>(a.fe, p, c, eta);
+        acc[1] += double(c);
+      }
+      if (a.flags & X_FWD_DERIV) {
+        T gc, ge[PMAX];
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i) ge[i] = T(0);
+        fe_grad<T, PMAX>(a.fe, p, c, eta, gc, ge);
+        pt[NX] = gc;
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i)
+          if (i < p) pt[(2 + i) * NX] = eta[i] - a.dtL * ge[i];
+      }
+    }
+  }
+  if (a.flags & X_ESUM) {
+    block_sum<2>(acc, red);
+    if (tid == 0) {
+      a.partials[2 * blockIdx.x + 0] = acc[0];
+      a.partials[2 * blockIdx.x + 1] = acc[1];
+    }
+  }
+  __syncthreads();
+
+  // phase 3: forward transforms of the slots
+  if (a.flags & (X_FWD_DERIV | X_FWD_RAW)) {
+    const bool deriv = (a.flags & X_FWD_DERIV) != 0;
+    const int nout = deriv ? F + 1 : F;
+    const int njobs = ROWS * nout;
+    for (int base = wave * UPW; base < njobs; base += NW * UPW) {
+      const int j = base + unit;
+      const int r = j / nout;
+      const int o = j - r * nout;
+      if (j < njobs && row0 + r < a.rows) {
+        const int sl = deriv ? o : (o == 0 ? 0 : o + 1);
+        c2<T>* ar = reinterpret_cast<c2<T>*>(rb + (r * SL + sl) * NX);
+        c2<T> v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = ar[t + TEAM * m];
+        team_sync<true>();
+        team_fft<T, NH, E, false, 1, true>(v, t, ar, tws);
+        team_sync<true>();
+#pragma unroll
+        for (int m = 0; m < E; ++m) ar[t + TEAM * m] = v[m];
+        team_sync<true>();
+        c2<T>* dst = a.b_out + o * a.fs_spec + (long long)(row0 + r) * a.Sx;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int k = t + TEAM * m;
+          const c2<T> Z = v[m];
+          const c2<T> Zc = conj<T>(ar[(NH - k) & (NH - 1)]);
+          const c2<T> sm = add<T>(Z, Zc);
+          const c2<T> d = sub<T>(Z, Zc);
+          const c2<T> B2 = mk<T>(d.y, -d.x);
+          const c2<T> WB = cmul<T>(B2, a.twx[k]);
+          dst[k] = mk<T>(T(0.5) * (sm.x + WB.x), T(0.5) * (sm.y + WB.y));
+          if (k == 0) dst[NH] = mk<T>(T(0.5) * (sm.x - B2.x), T(0.5) * (sm.y - B2.y));
+        }
+      }
+    }
   }
 }
 
@@ -281,14 +460,16 @@ adj_row_kernel(AdjArgs<T> a) {
   c2<T>* my = lds + team * G::REGION;
   const int F = a.F;
   const int p = F - 1;
+  Twiddles<T, G::NH, E> tws;
+  tws.load(t, a.twx, 2);
 
   // w[0] = e_c, w[1..p] = e_i, bc = b_c; w is overwritten by lambda^n
   c2<T> w[FB][E], bc[E];
-  row_c2r<T, NX, E>(w[0], a.s_in + rrow * a.Sx, active, t, my, a.twx);
-  row_c2r<T, NX, E>(bc, a.s_in + a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+  row_c2r<T, NX, E>(w[0], a.s_in + rrow * a.Sx, active, t, my, a.twx, tws);
+  row_c2r<T, NX, E>(bc, a.s_in + a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
 #pragma unroll
   for (int i = 0; i < PMAX; ++i)
-    if (i < p) row_c2r<T, NX, E>(w[1 + i], a.s_in + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+    if (i < p) row_c2r<T, NX, E>(w[1 + i], a.s_in + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
 
   double q[4] = {0.0, 0.0, 0.0, 0.0};
   const double cmean = *a.mean_c;
@@ -355,7 +536,7 @@ adj_row_kernel(AdjArgs<T> a) {
   if (a.do_fwd) {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
-      if (f < F) row_r2c<T, NX, E>(w[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx);
+      if (f < F) row_r2c<T, NX, E>(w[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
   }
 }
 
@@ -383,37 +564,48 @@ struct ColArgs {
   T dtM, dtMkc, dtL, dtLke, invP;
 };
 
-// E elements per lane; C columns per work-group (C * 8 or 16 bytes per row
-// segment), at least one wavefront and at most 512 lanes per group (so a
-// lane may use up to 256 VGPRs), and at most 128 KiB of LDS.
+// Column-pass geometry.  E = 8 elements per lane (N / 8 lanes per column),
+// C consecutive columns per work-group: 32-byte row segments for the long
+// axes (N >= 512) so that a 2D grid still yields several work-groups per
+// compute unit, 128-byte segments otherwise; at least one wavefront and at
+// most 512 lanes per group.
 template <typename T, int N>
 struct ColGeom {
-  static constexpr int E = N <= 8 ? N : ((N <= 512 || sizeof(T) == 8) ? 8 : 16);
+  static constexpr int E = N <= 8 ? N : 8;
   static constexpr int TEAM = N / E;
-  static constexpr int CB = sizeof(T) == 8 ? 8 : 16;  // 128-byte row segments
-  static constexpr int LDSMAX = 128 * 1024;
+  static constexpr int CB = N >= 512 ? (sizeof(T) == 8 ? 2 : 4) : (sizeof(T) == 8 ? 8 : 16);
   static constexpr int C0 = (CB * TEAM < 64) ? 64 / TEAM : CB;
-  static constexpr int C1 = (C0 * TEAM > 512) ? 512 / TEAM : C0;
-  static constexpr int C = (C1 * N * (int)sizeof(c2<T>) > LDSMAX) ? LDSMAX / (N * (int)sizeof(c2<T>)) : C1;
+  static constexpr int C = (C0 * TEAM > 512) ? (512 / TEAM > 0 ? 512 / TEAM : 1) : C0;
   static constexpr int WG = C * TEAM;
 };
 
+// One work-group per (column tile, outer index, field group).  Field groups:
+// forward/inverse: one per field; update and adjoint: the c group (which
+// needs c^ and g^ together) and one per eta_i; energy: one per field.
+// Blocks are dealt to the eight XCDs round-robin (block b runs on XCD b % 8),
+// so the logical work index is chosen to give each XCD a contiguous run of
+// tiles: tiles that share a cache line then share one L2.
 template <typename T, int N>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, ColGeom<T, N>::WG)))
-col_kernel(ColArgs<T> a) {
+col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   using G = ColGeom<T, N>;
   constexpr int E = G::E, TEAM = G::TEAM, C = G::C;
+  const int b = blockIdx.x;
+  const int L = (b & 7) * nslots + (b >> 3);
+  if (L >= tiles * nouter * ngroups) return;
+  const int tile = L % tiles;
+  const int rest = L / tiles;
+  const int o = rest % nouter;
+  const int g = rest / nouter;
   __shared__ c2<T> lds[N * C];
   __shared__ double red[2 * (G::WG / 64 + 1)];
   const int lane = threadIdx.x;
   const int cc = lane % C;
   const int t = lane / C;
-  const int col = blockIdx.x * C + cc;
-  const int o = blockIdx.y;
+  const int col = tile * C + cc;
   const bool active = col < a.ncols;
   const long long base = (long long)o * a.os + (active ? col : 0);
   c2<T>* my = lds + cc;
-  const int F = a.F;
 
   auto load = [&](const c2<T>* src, c2<T>* v) {
 #pragma unroll
@@ -427,67 +619,69 @@ col_kernel(ColArgs<T> a) {
     }
   };
   const T kc = a.kcol[active ? col : 0] + (a.kouter ? a.kouter[o] : T(0));
+  Twiddles<T, N, E> tws;
+  tws.load(t, a.tw, 1);
 
   c2<T> v[E];
   if (a.mode == COL_FWD || a.mode == COL_INV) {
-    for (int f = 0; f < F; ++f) {
-      load(a.src + f * a.fs_src, v);
-      if (a.mode == COL_FWD) team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
-      else team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
-      store(a.dst + f * a.fs_dst, v);
-    }
+    load(a.src + g * a.fs_src, v);
+    if (a.mode == COL_FWD) team_fft<T, N, E, false, C>(v, t, my, tws);
+    else team_fft<T, N, E, true, C>(v, t, my, tws);
+    store(a.dst + g * a.fs_dst, v);
   } else if (a.mode == COL_UPDATE) {
-    // c: (c^ - dt M k2 g^) / (1 + dt M kappa_c k2^2), the k = 0 mode held in double
-    c2<T> g[E];
-    load(a.src, v);
-    load(a.src + a.fs_src, g);
-    team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
-    team_fft<T, N, E, false, C>(g, t, my, a.tw, 1);
+    if (g == 0) {
+      // c: (c^ - dt M k2 g^) / (1 + dt M kappa_c k2^2); the k = 0 mode held in double
+      c2<T> gg[E];
+      load(a.src, v);
+      load(a.src + a.fs_src, gg);
+      team_fft<T, N, E, false, C>(v, t, my, tws);
+      team_fft<T, N, E, false, C>(gg, t, my, tws);
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int e = t + TEAM * m;
-      const T k2 = kc + a.kaxis[e];
-      const T D = a.invP / (T(1) + a.dtMkc * k2 * k2);
-      const T s = a.dtM * k2;
-      v[m] = mk<T>((v[m].x - s * g[m].x) * D, (v[m].y - s * g[m].y) * D);
-      if (col == 0 && o == 0 && e == 0) v[m] = mk<T>(T(*a.mean_c), T(0));
-    }
-    team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
-    store(a.dst, v);
-    // eta_i: b^ / (1 + dt L kappa_eta k2)
-    for (int f = 1; f < F; ++f) {
-      load(a.src + (f + 1) * a.fs_src, v);
-      team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
+      for (int m = 0; m < E; ++m) {
+        const int e = t + TEAM * m;
+        const T k2 = kc + a.kaxis[e];
+        const T D = a.invP / (T(1) + a.dtMkc * k2 * k2);
+        const T sk = a.dtM * k2;
+        v[m] = mk<T>((v[m].x - sk * gg[m].x) * D, (v[m].y - sk * gg[m].y) * D);
+        if (col == 0 && o == 0 && e == 0) v[m] = mk<T>(T(*a.mean_c), T(0));
+      }
+      team_fft<T, N, E, true, C>(v, t, my, tws);
+      store(a.dst, v);
+    } else {
+      // eta_g: b^ / (1 + dt L kappa_eta k2)
+      load(a.src + (g + 1) * a.fs_src, v);
+      team_fft<T, N, E, false, C>(v, t, my, tws);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
         const T D = a.invP / (T(1) + a.dtLke * k2);
         v[m] = mk<T>(v[m].x * D, v[m].y * D);
       }
-      team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
-      store(a.dst + f * a.fs_dst, v);
+      team_fft<T, N, E, true, C>(v, t, my, tws);
+      store(a.dst + g * a.fs_dst, v);
     }
   } else if (a.mode == COL_ADJ) {
-    // lambda^ -> e_c = x/(1+x) lambda_c^ (x = dt M kappa_c k2^2), b_c = D_c k2 lambda_c^,
-    //            e_i = y/(1+y) lambda_i^ (y = dt L kappa_eta k2)
-    c2<T> b[E];
-    load(a.src, v);
-    team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
+    if (g == 0) {
+      // e_c = x/(1+x) lambda_c^ (x = dt M kappa_c k2^2), b_c = D_c k2 lambda_c^
+      c2<T> bb[E];
+      load(a.src, v);
+      team_fft<T, N, E, false, C>(v, t, my, tws);
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const T k2 = kc + a.kaxis[t + TEAM * m];
-      const T x = a.dtMkc * k2 * k2;
-      const T D = a.invP / (T(1) + x);
-      b[m] = mk<T>(v[m].x * D * k2, v[m].y * D * k2);
-      v[m] = mk<T>(v[m].x * D * x, v[m].y * D * x);
-    }
-    team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
-    store(a.dst, v);
-    team_fft<T, N, E, true, C>(b, t, my, a.tw, 1);
-    store(a.dst + a.fs_dst, b);
-    for (int f = 1; f < F; ++f) {
-      load(a.src + f * a.fs_src, v);
-      team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
+      for (int m = 0; m < E; ++m) {
+        const T k2 = kc + a.kaxis[t + TEAM * m];
+        const T x = a.dtMkc * k2 * k2;
+        const T D = a.invP / (T(1) + x);
+        bb[m] = mk<T>(v[m].x * D * k2, v[m].y * D * k2);
+        v[m] = mk<T>(v[m].x * D * x, v[m].y * D * x);
+      }
+      team_fft<T, N, E, true, C>(v, t, my, tws);
+      store(a.dst, v);
+      team_fft<T, N, E, true, C>(bb, t, my, tws);
+      store(a.dst + a.fs_dst, bb);
+    } else {
+      // e_g = y/(1+y) lambda_g^ (y = dt L kappa_eta k2)
+      load(a.src + g * a.fs_src, v);
+      team_fft<T, N, E, false, C>(v, t, my, tws);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
@@ -495,29 +689,26 @@ col_kernel(ColArgs<T> a) {
         const T D = a.invP * y / (T(1) + y);
         v[m] = mk<T>(v[m].x * D, v[m].y * D);
       }
-      team_fft<T, N, E, true, C>(v, t, my, a.tw, 1);
-      store(a.dst + (f + 1) * a.fs_dst, v);
+      team_fft<T, N, E, true, C>(v, t, my, tws);
+      store(a.dst + (g + 1) * a.fs_dst, v);
     }
-  } else {  // COL_ENERGY
+  } else {  // COL_ENERGY: sum of w_kx k2 |u^|^2 of field g
     double acc[2] = {0.0, 0.0};
     const double wcol = (col == 0 || col == a.nyq) ? 1.0 : 2.0;
-    for (int f = 0; f < F; ++f) {
-      load(a.src + f * a.fs_src, v);
-      team_fft<T, N, E, false, C>(v, t, my, a.tw, 1);
-      if (active) {
+    load(a.src + g * a.fs_src, v);
+    team_fft<T, N, E, false, C>(v, t, my, tws);
+    if (active) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-          const double k2 = double(kc) + double(a.kaxis[t + TEAM * m]);
-          const double re = double(v[m].x), im = double(v[m].y);
-          acc[f == 0 ? 0 : 1] += wcol * k2 * (re * re + im * im);
-        }
+      for (int m = 0; m < E; ++m) {
+        const double k2 = double(kc) + double(a.kaxis[t + TEAM * m]);
+        const double re = double(v[m].x), im = double(v[m].y);
+        acc[g == 0 ? 0 : 1] += wcol * k2 * (re * re + im * im);
       }
     }
     block_sum<2>(acc, red);
     if (threadIdx.x == 0) {
-      const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-      a.partials[2 * b + 0] = acc[0];
-      a.partials[2 * b + 1] = acc[1];
+      a.partials[2 * (long long)L + 0] = acc[0];
+      a.partials[2 * (long long)L + 1] = acc[1];
     }
   }
 }

@@ -587,7 +587,7 @@ pf_status pf_create(const pf_config* cfg, pf_handle** out) {
     off = align256(off + h->kt[ax].size() * h->es);
   }
   long long np = h->rows;
-  np = std::max<long long>(np, (long long)h->nxh * std::max(h->ny, h->nz));
+  np = std::max<long long>(np, (long long)h->nxh * std::max(h->ny, h->nz) * (h->F + 1));
   np = std::max<long long>(np, (h->P + 255) / 256);
   h->nparts = np;
   h->off_part = off;

@@ -38,19 +38,24 @@ def log(*a):
 
 
 def algorithmic_bytes(cfg, prec, kind):
-    """Compulsory HBM bytes of one launch of a pass over the whole grid.
+    """Compulsory HBM bytes of one launch of a 2D pass over the whole grid,
+    each input read once and each output written once.
 
-    Both passes of a 2D FS step read and write x-spectra only: the row pass
-    reads F x-spectra and writes F + 1, the column pass reads F + 1 and
-    writes F, each x-spectrum holding (Nx/2 + 1) complex values per row.
+    Row pass: reads the F state x-spectra, writes the F right-hand-side
+    x-spectra (df/dc and eta_i - dt L df/deta_i).  Column pass: reads those F
+    plus the carried spectrum of c, writes the F new state x-spectra plus the
+    carried spectrum.  An x-spectrum field holds (Nx/2 + 1) complex values
+    per row.
     """
     F = 1 + cfg["p"]
     nx, ny = cfg["n"][0], cfg["n"][1]
     nz = cfg["n"][2] if cfg["ndim"] == 3 else 1
     s = 4 if prec == "f32" else 8
     spec = (nx // 2 + 1) * ny * nz * 2 * s  # one x-spectrum field
-    if kind in ("row", "col"):
-        return (2 * F + 1) * spec
+    if kind == "row":
+        return 2 * F * spec
+    if kind == "col":
+        return (2 * F + 2) * spec
     raise ValueError(kind)
 
 
@@ -176,7 +181,12 @@ def main(argv=None):
            "config": {"workload": "FS step, 2D 1024x1024 periodic, dx=1, c + 4 eta (F=5), paper "
                                   "f_chem, seeded uniform IC c=0.5+0.05U(-1,1), eta=0.1U(0,1), dt=0.1",
                       "grid": [1024, 1024], "fields": 5, "dt": dt, "precision": "f32"},
-           "roofline": roof}
+           "roofline": roof,
+           # whole step against the survey's unfused Algorithm 1 figure of
+           # 9 F s bytes per grid point (F = 5, s = 4)
+           "step_roofline_9Fs": {"bytes_per_point": 9 * 5 * 4,
+                                 "achieved_GBs": round(value * 9 * 5 * 4 / 1e9, 1),
+                                 "frac": round(value * 9 * 5 * 4 / (HBM_PEAK_GBS * 1e9), 4)}}
     del s32
     torch.cuda.empty_cache()
 

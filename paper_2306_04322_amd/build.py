@@ -20,8 +20,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpfspec.so")
 
-SOURCES = ["pfspec.hip", "k_row_f32.hip", "k_row_f64.hip", "k_col.hip", "k_fd.hip",
-           "k_adj_f32.hip", "k_adj_f64.hip"]
+SOURCES = ["pfspec.hip", "k_row_f32.hip", "k_row_f64.hip", "k_col_f32.hip", "k_col_f64.hip",
+           "k_reduce.hip", "k_fd.hip", "k_adj_f32.hip", "k_adj_f64.hip"]
 
 ARCH = "gfx950"
 CFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-fno-gpu-rdc",
@@ -48,37 +48,44 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + CFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src, defines=(), build_dir=BUILD):
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc()] + CFLAGS + ["-D" + d for d in defines] + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
     return obj
 
 
-def build(jobs=None, verbose=True):
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs=None, verbose=True, defines=(), out=None):
+    """Compile and link.  `defines` (NAME=VALUE strings) override the kernel
+    tuning parameters; `out` writes the library elsewhere (tuning sweeps)."""
+    lib = out or LIB
+    build_dir = BUILD if not defines else os.path.join(BUILD, "variant_" + "_".join(defines).replace("=", ""))
+    os.makedirs(build_dir, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, defines, build_dir), srcs))
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (r.stdout, r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("-D", dest="defines", action="append", default=[],
+                    help="override a kernel tuning parameter, e.g. -D PF_COL_CB_LONG_F32=8")
+    ap.add_argument("-o", dest="out", default=None, help="output library path")
     args = ap.parse_args(argv)
-    build(args.j)
+    build(args.j, defines=args.defines, out=args.out)
 
 
 if __name__ == "__main__":

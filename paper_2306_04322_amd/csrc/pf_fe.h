@@ -18,15 +18,19 @@ struct FeParams {
             // POLY:  c_alpha, c_beta, c_m, A, B, D, gamma, delta, eps
 };
 
-// df/dc and df/deta_i at one point.
-template <typename T, int PMAX>
-__device__ __forceinline__ void fe_grad(const FeParams<T>& P, int p, T c, const T* eta,
+// df/dc and df/deta_i at one point.  PX > 0 fixes p = PX and FEK >= 0 the
+// free-energy kind at compile time (the steady-state kernels); otherwise
+// both come from the arguments.
+template <typename T, int PMAX, int FEK = -1, int PX = 0>
+__device__ __forceinline__ void fe_grad(const FeParams<T>& P, int p_rt, T c, const T* eta,
                                         T& gc, T* ge) {
+  const int p = PX > 0 ? PX : p_rt;
+  const int kind = FEK >= 0 ? FEK : P.kind;
   T s2 = T(0);
 #pragma unroll
   for (int i = 0; i < PMAX; ++i)
     if (i < p) s2 += eta[i] * eta[i];
-  if (P.kind == FE_PAPER) {
+  if (kind == FE_PAPER) {
     const T rho2 = P.k[0], ca = P.k[1], cb = P.k[2], w = P.k[3], al = P.k[4];
     T H = T(0);
 #pragma unroll

@@ -58,6 +58,14 @@ __device__ __forceinline__ c2<T> scale(c2<T> a, T s) { return mk<T>(a.x * s, a.y
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
+// LDS position of exchange element i: one padding slot after every eight
+// elements.  The Stockham writes of a pass land at strides of 8 R or 64
+// elements across lanes, which without padding fall into the same LDS banks;
+// with it they spread over all banks.  An exchange area of N elements
+// occupies lds_span(N) slots.
+__device__ __forceinline__ constexpr int pad(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int lds_span(int n) { return n + (n >> 3) + 1; }
+
 // Multiply by exp(-2 pi i K / R) (forward) or exp(+2 pi i K / R) (inverse)
 // for R <= 16, 0 <= K < R/2.  Exact sixteenth roots of unity: cos(pi/8),
 // sin(pi/8) and sqrt(1/2) to 23 digits.
@@ -160,7 +168,7 @@ struct Twiddles {
 };
 
 // One Stockham pass.  `lds` points at element 0 of this team's exchange
-// area; element i lives at lds[i * LS].  `tw` holds this pass's twiddles
+// area; element i lives at lds[pad(i) * LS].  `tw` holds this pass's twiddles
 // (radix-E passes after the first only).
 template <typename T, int N, int E, int R, int NS, bool INV, bool LAST, int LS>
 __device__ __forceinline__ void stockham_pass(c2<T>* v, int t, c2<T>* lds, const c2<T>* tw) {
@@ -185,7 +193,7 @@ __device__ __forceinline__ void stockham_pass(c2<T>* v, int t, c2<T>* lds, const
     } else {
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[(base + r * NS) * LS] = x[r];
+      for (int r = 0; r < R; ++r) lds[pad(base + r * NS) * LS] = x[r];
     }
   }
 }
@@ -205,19 +213,26 @@ __device__ __forceinline__ void team_sync() {
   }
 }
 
+// Passes of one team transform.  With a second exchange area (`lds2`
+// non-null, work-group teams only) consecutive exchanges alternate between
+// the two areas, so one barrier per exchange suffices: the next pass writes
+// the area nobody is reading.  `par` is the parity of the exchanges already
+// made by earlier transforms, so alternation continues across transforms.
 template <typename T, int N, int E, bool INV, int NS, int LS, bool WAVE, int PI>
 struct FftPasses {
   static constexpr int R = (NS == 1) ? first_radix<N, E>() : E;
   static constexpr bool LAST = (NS * R == N);
-  __device__ __forceinline__ static void run(c2<T>* v, int t, c2<T>* lds, const c2<T>* twr) {
-    stockham_pass<T, N, E, R, NS, INV, LAST, LS>(v, t, lds, twr + (PI > 0 ? (PI - 1) * (E - 1) : 0));
+  __device__ __forceinline__ static void run(c2<T>* v, int t, c2<T>* lds, c2<T>* lds2,
+                                             const c2<T>* twr, int par) {
+    c2<T>* area = (lds2 && ((PI + par) & 1)) ? lds2 : lds;
+    stockham_pass<T, N, E, R, NS, INV, LAST, LS>(v, t, area, twr + (PI > 0 ? (PI - 1) * (E - 1) : 0));
     if constexpr (!LAST) {
       constexpr int TEAM = N / E;
       team_sync<WAVE>();
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = lds[(t + TEAM * m) * LS];
-      team_sync<WAVE>();
-      FftPasses<T, N, E, INV, NS * R, LS, WAVE, PI + 1>::run(v, t, lds, twr);
+      for (int m = 0; m < E; ++m) v[m] = area[pad(t + TEAM * m) * LS];
+      if (!lds2) team_sync<WAVE>();
+      FftPasses<T, N, E, INV, NS * R, LS, WAVE, PI + 1>::run(v, t, lds, lds2, twr, par);
     }
   }
 };
@@ -226,12 +241,19 @@ struct FftPasses {
 // holds the lane's twiddles (Twiddles<T, N, E>::load).  With WAVE = false
 // every lane of the work-group must call this (it contains work-group
 // barriers); with WAVE = true the team must lie within one wavefront and
-// only that team's lanes take part.
+// only that team's lanes take part.  `lds2`, when given (WAVE = false only),
+// is a second exchange area of the same size; `par` is the exchange parity
+// returned by the previous transform that used the same two areas (0 for
+// the first), and the new parity is returned.  With two areas the caller
+// must not touch either area between the transform's return and the next
+// work-group barrier of its own (the last exchange may still be read).
 template <typename T, int N, int E, bool INV, int LS, bool WAVE = false>
-__device__ __forceinline__ void team_fft(c2<T>* v, int t, c2<T>* lds, const Twiddles<T, N, E>& tw) {
+__device__ __forceinline__ int team_fft(c2<T>* v, int t, c2<T>* lds, const Twiddles<T, N, E>& tw,
+                                        c2<T>* lds2 = nullptr, int par = 0) {
   static_assert(N >= E && E >= 2 && (N % E) == 0, "bad FFT team shape");
   static_assert(!WAVE || N / E <= 64, "a wave-synchronised team must fit one wavefront");
-  FftPasses<T, N, E, INV, 1, LS, WAVE, 0>::run(v, t, lds, tw.w);
+  FftPasses<T, N, E, INV, 1, LS, WAVE, 0>::run(v, t, lds, lds2, tw.w, par);
+  return par + Twiddles<T, N, E>::P - 1;
 }
 
 }  // namespace pf

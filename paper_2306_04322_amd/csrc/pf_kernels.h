@@ -27,14 +27,36 @@
 #include "pf_fe.h"
 #include "pf_fft.h"
 
+// Tuning parameters (compile-time; the defaults are the measured best on
+// MI355X for the 2D 1024^2 and 3D 256^3 workloads).
+#ifndef PF_COL_CB_LONG_F32
+#define PF_COL_CB_LONG_F32 4  // columns per tile, float, transform length >= 512
+#endif
+#ifndef PF_COL_CB_LONG_F64
+#define PF_COL_CB_LONG_F64 2  // columns per tile, double, transform length >= 512
+#endif
+#ifndef PF_COL_MIN_WAVES
+#define PF_COL_MIN_WAVES 1  // register budget of the column pass (waves per SIMD)
+#endif
+#ifndef PF_ROW_MIN_WAVES
+#define PF_ROW_MIN_WAVES 1  // register budget of the steady-state row pass
+#endif
+#ifndef PF_ROW_NW
+#define PF_ROW_NW 4  // wavefronts per row-pass work-group (0: p_max + 1)
+#endif
+#ifndef PF_COL_E_LONG_F32
+#define PF_COL_E_LONG_F32 8  // elements per lane, float column transforms of length >= 512
+#endif
+
 namespace pf {
 
 enum {
   X_LOAD_REAL = 1,   // read real rows (else C2R of s_in)
   X_STORE_REAL = 2,  // write the real rows to u_out
-  X_FWD_DERIV = 4,   // R2C of [c, df/dc, eta_i - dt L df/deta_i] -> b_out (F+1 fields)
+  X_FWD_DERIV = 4,   // R2C of [df/dc, eta_i - dt L df/deta_i] -> b_out fields 1..F
   X_FWD_RAW = 8,     // R2C of the F real rows as they are -> b_out
-  X_ESUM = 16        // double sums of f(u) and c -> partials[block][2]
+  X_ESUM = 16,       // double sums of f(u) and c -> partials[block][2]
+  X_WITH_C = 32      // with X_FWD_DERIV: also R2C of c -> b_out field 0
 };
 
 template <typename T>
@@ -61,7 +83,7 @@ struct XGeom {
   static constexpr int TEAM = NH / E;
   static constexpr int ROWS = TEAM >= 64 ? 1 : 64 / TEAM;
   static constexpr int WG = ROWS * TEAM;
-  static constexpr int REGION = NH + 1;  // LDS complex values per team
+  static constexpr int REGION = lds_span(NH) + 1;  // LDS complex values per team
 };
 
 // C2R of one row: x-spectrum src[0..NH] -> v[m] = (x[2k], x[2k+1]),
@@ -187,7 +209,7 @@ xpass_kernel(XArgs<T> a) {
   }
 
   if (a.flags & X_FWD_DERIV) {
-    // outputs: 0 -> c, 1 -> df/dc, 2 + i -> eta_i - dt L df/deta_i
+    // outputs: 0 -> c (X_WITH_C only), 1 -> df/dc, 2 + i -> eta_i - dt L df/deta_i
     c2<T> gcv[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -213,7 +235,8 @@ xpass_kernel(XArgs<T> a) {
       }
       gcv[m] = mk<T>(gcx, gcy);
     }
-    row_r2c<T, NX, E>(u[0], a.b_out + 0 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
+    if (a.flags & X_WITH_C)
+      row_r2c<T, NX, E>(u[0], a.b_out + 0 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
     row_r2c<T, NX, E>(gcv, a.b_out + 1 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
 #pragma unroll
     for (int i = 0; i < PMAX; ++i)
@@ -246,21 +269,31 @@ struct RGeom {
   static constexpr bool WAVE_OK = TEAM <= 64;
   static constexpr int UPW = WAVE_OK ? 64 / TEAM : 1;  // transforms per wavefront
   static constexpr int ROWS = NX >= 1024 ? 1 : 1024 / NX;
-  static constexpr int NW = 4;
+  static constexpr int NW = PF_ROW_NW > 0 ? PF_ROW_NW : PMAX + 1;  // one transform per wave and phase when F = PMAX + 1
   static constexpr int WG = 64 * NW;
   static constexpr int SLOTS = PMAX + 2;
-  static constexpr long LDS_BYTES = long(ROWS) * SLOTS * NX * long(sizeof(T));
+  static constexpr int SLOT_C = lds_span(NH);  // complex values per slot (padded layout)
+  static constexpr long LDS_BYTES = long(ROWS) * SLOTS * SLOT_C * 2 * long(sizeof(T));
   static constexpr bool FITS = WAVE_OK && LDS_BYTES <= 96 * 1024;
+  // register budget: enough waves per SIMD for four work-groups per CU
+  static constexpr int MIN_WAVES = (sizeof(T) == 4 && PMAX <= 4) ? PF_ROW_MIN_WAVES : 1;
 };
 
-template <typename T, int NX, int PMAX>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, RGeom<T, NX, PMAX>::WG)))
+// FX >= 0 fixes the flags at compile time apart from X_STORE_REAL (the
+// steady-state step gets a lean instantiation); FX = -1 reads them from the
+// arguments.  FEK >= 0
+// fixes the free-energy kind and requires p = PMAX.
+template <typename T, int NX, int PMAX, int FX, int FEK = -1>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, RGeom<T, NX, PMAX>::WG),
+                               amdgpu_waves_per_eu(FX >= 0 ? RGeom<T, NX, PMAX>::MIN_WAVES : 1)))
 rowpass_kernel(XArgs<T> a) {
   using G = RGeom<T, NX, PMAX>;
   constexpr int NH = G::NH, E = G::E, TEAM = G::TEAM, UPW = G::UPW, ROWS = G::ROWS;
-  constexpr int NW = G::NW, SL = G::SLOTS, WG = G::WG;
+  constexpr int NW = G::NW, SL = G::SLOTS, WG = G::WG, SC = G::SLOT_C;
   static_assert(G::FITS, "row pass v2 does not fit this size");
-  __shared__ __align__(16) T rb[ROWS * SL * NX];
+  // slot (r, s) holds real row r of slot s as complex pairs (x[2q], x[2q+1])
+  // at padded position pad(q)
+  __shared__ __align__(16) c2<T> rb[ROWS * SL * SC];
   __shared__ double red[2 * (NW + 1)];
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -270,11 +303,14 @@ rowpass_kernel(XArgs<T> a) {
   const int row0 = blockIdx.x * ROWS;
   const int F = a.F;
   const int p = F - 1;
+  // the store flag stays a run-time choice even in the fixed instantiations,
+  // so a recomputation that also stores the states runs the same arithmetic
+  const int flags = FX >= 0 ? (FX | (a.flags & X_STORE_REAL)) : a.flags;
   Twiddles<T, NH, E> tws;
   tws.load(t, a.twx, 2);
 
   // phase 1: real rows into the row buffer
-  if (a.flags & X_LOAD_REAL) {
+  if (flags & X_LOAD_REAL) {
     const int n2 = ROWS * F * NH;
     for (int q = tid; q < n2; q += WG) {
       const int x2 = q % NH;
@@ -284,8 +320,8 @@ rowpass_kernel(XArgs<T> a) {
       const int row = row0 + r;
       if (row < a.rows) {
         const c2<T>* src = reinterpret_cast<const c2<T>*>(a.u_in + f * a.fs_real + (long long)row * NX);
-        c2<T>* ar = reinterpret_cast<c2<T>*>(rb + (r * SL + (f == 0 ? 0 : f + 1)) * NX);
-        ar[x2] = src[x2];
+        c2<T>* ar = rb + (r * SL + (f == 0 ? 0 : f + 1)) * SC;
+        ar[pad(x2)] = src[x2];
       }
     }
   } else {
@@ -296,7 +332,7 @@ rowpass_kernel(XArgs<T> a) {
       const int f = j - r * F;
       if (j < njobs && row0 + r < a.rows) {
         const c2<T>* src = a.s_in + f * a.fs_spec + (long long)(row0 + r) * a.Sx;
-        c2<T>* ar = reinterpret_cast<c2<T>*>(rb + (r * SL + (f == 0 ? 0 : f + 1)) * NX);
+        c2<T>* ar = rb + (r * SL + (f == 0 ? 0 : f + 1)) * SC;
         c2<T> v[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -310,49 +346,60 @@ rowpass_kernel(XArgs<T> a) {
         team_fft<T, NH, E, true, 1, true>(v, t, ar, tws);
         team_sync<true>();
 #pragma unroll
-        for (int m = 0; m < E; ++m) ar[t + TEAM * m] = v[m];
+        for (int m = 0; m < E; ++m) ar[pad(t + TEAM * m)] = v[m];
       }
     }
   }
   __syncthreads();
 
-  // phase 2: pointwise work on the row buffer
+  // phase 2: pointwise work on the row buffer, two adjacent points per lane
   double acc[2] = {0.0, 0.0};
-  const int npts = ROWS * NX;
-  for (int q = tid; q < npts; q += WG) {
-    const int r = q / NX;
-    const int x = q - r * NX;
+  const int pp = FEK >= 0 ? PMAX : p;
+  const int npairs = ROWS * NH;
+  for (int q = tid; q < npairs; q += WG) {
+    const int r = q / NH;
+    const int x2 = q - r * NH;
     const int row = row0 + r;
     if (row < a.rows) {
-      T* pt = rb + r * SL * NX + x;
-      const T c = pt[0];
-      T eta[PMAX];
+      c2<T>* pt = rb + r * SL * SC + pad(x2);
+      const c2<T> c = pt[0];
+      c2<T> eta[PMAX];
 #pragma unroll
-      for (int i = 0; i < PMAX; ++i) eta[i] = (i < p) ? pt[(2 + i) * NX] : T(0);
-      if (a.flags & X_STORE_REAL) {
-        const long long off = (long long)row * NX + x;
-        a.u_out[off] = c;
-#pragma unroll
-        for (int i = 0; i < PMAX; ++i)
-          if (i < p) a.u_out[(1 + i) * a.fs_real + off] = eta[i];
-      }
-      if (a.flags & X_ESUM) {
-        acc[0] += fe_density<T, PMAX>(a.fe, p, c, eta);
-        acc[1] += double(c);
-      }
-      if (a.flags & X_FWD_DERIV) {
-        T gc, ge[PMAX];
-#pragma unroll
-        for (int i = 0; i < PMAX; ++i) ge[i] = T(0);
-        fe_grad<T, PMAX>(a.fe, p, c, eta, gc, ge);
-        pt[NX] = gc;
+      for (int i = 0; i < PMAX; ++i) eta[i] = (i < pp) ? pt[(2 + i) * SC] : mk<T>(T(0), T(0));
+      if (flags & X_STORE_REAL) {
+        const long long off = (long long)row * NH + x2;
+        reinterpret_cast<c2<T>*>(a.u_out)[off] = c;
 #pragma unroll
         for (int i = 0; i < PMAX; ++i)
-          if (i < p) pt[(2 + i) * NX] = eta[i] - a.dtL * ge[i];
+          if (i < pp) reinterpret_cast<c2<T>*>(a.u_out + (1 + i) * a.fs_real)[off] = eta[i];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const T ch = h ? c.y : c.x;
+        T e[PMAX];
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i) e[i] = h ? eta[i].y : eta[i].x;
+        if (flags & X_ESUM) {
+          acc[0] += fe_density<T, PMAX>(a.fe, pp, ch, e);
+          acc[1] += double(ch);
+        }
+        if (flags & X_FWD_DERIV) {
+          T gc, ge[PMAX];
+#pragma unroll
+          for (int i = 0; i < PMAX; ++i) ge[i] = T(0);
+          fe_grad<T, PMAX, FEK, (FEK >= 0 ? PMAX : 0)>(a.fe, pp, ch, e, gc, ge);
+          if (h) pt[SC].y = gc; else pt[SC].x = gc;
+#pragma unroll
+          for (int i = 0; i < PMAX; ++i)
+            if (i < pp) {
+              const T bi = e[i] - a.dtL * ge[i];
+              if (h) pt[(2 + i) * SC].y = bi; else pt[(2 + i) * SC].x = bi;
+            }
+        }
       }
     }
   }
-  if (a.flags & X_ESUM) {
+  if (flags & X_ESUM) {
     block_sum<2>(acc, red);
     if (tid == 0) {
       a.partials[2 * blockIdx.x + 0] = acc[0];
@@ -362,32 +409,33 @@ rowpass_kernel(XArgs<T> a) {
   __syncthreads();
 
   // phase 3: forward transforms of the slots
-  if (a.flags & (X_FWD_DERIV | X_FWD_RAW)) {
-    const bool deriv = (a.flags & X_FWD_DERIV) != 0;
-    const int nout = deriv ? F + 1 : F;
+  if (flags & (X_FWD_DERIV | X_FWD_RAW)) {
+    const bool deriv = (flags & X_FWD_DERIV) != 0;
+    const int skip = (deriv && !(flags & X_WITH_C)) ? 1 : 0;  // output 0 (c) not needed
+    const int nout = deriv ? F + 1 - skip : F;
     const int njobs = ROWS * nout;
     for (int base = wave * UPW; base < njobs; base += NW * UPW) {
       const int j = base + unit;
       const int r = j / nout;
-      const int o = j - r * nout;
+      const int o = j - r * nout + skip;
       if (j < njobs && row0 + r < a.rows) {
         const int sl = deriv ? o : (o == 0 ? 0 : o + 1);
-        c2<T>* ar = reinterpret_cast<c2<T>*>(rb + (r * SL + sl) * NX);
+        c2<T>* ar = rb + (r * SL + sl) * SC;
         c2<T> v[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = ar[t + TEAM * m];
+        for (int m = 0; m < E; ++m) v[m] = ar[pad(t + TEAM * m)];
         team_sync<true>();
         team_fft<T, NH, E, false, 1, true>(v, t, ar, tws);
         team_sync<true>();
 #pragma unroll
-        for (int m = 0; m < E; ++m) ar[t + TEAM * m] = v[m];
+        for (int m = 0; m < E; ++m) ar[pad(t + TEAM * m)] = v[m];
         team_sync<true>();
         c2<T>* dst = a.b_out + o * a.fs_spec + (long long)(row0 + r) * a.Sx;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
           const int k = t + TEAM * m;
           const c2<T> Z = v[m];
-          const c2<T> Zc = conj<T>(ar[(NH - k) & (NH - 1)]);
+          const c2<T> Zc = conj<T>(ar[pad((NH - k) & (NH - 1))]);
           const c2<T> sm = add<T>(Z, Zc);
           const c2<T> d = sub<T>(Z, Zc);
           const c2<T> B2 = mk<T>(d.y, -d.x);
@@ -440,7 +488,7 @@ struct AGeom {
   static constexpr int TEAM = NH / E;
   static constexpr int ROWS = TEAM >= 64 ? 1 : 64 / TEAM;
   static constexpr int WG = ROWS * TEAM;
-  static constexpr int REGION = NH + 1;
+  static constexpr int REGION = lds_span(NH) + 1;
 };
 
 template <typename T, int NX, int PMAX>
@@ -543,7 +591,8 @@ adj_row_kernel(AdjArgs<T> a) {
 // ---------------------------------------------------------------------------
 // Column pass.
 
-enum { COL_FWD = 0, COL_INV = 1, COL_UPDATE = 2, COL_ADJ = 3, COL_ENERGY = 4 };
+enum { COL_FWD = 0, COL_INV = 1, COL_UPDATE = 2, COL_ADJ = 3, COL_ENERGY = 4,
+       COL_UPDATE_FIRST = 5 /* launch-time only: COL_UPDATE with first = 1 */ };
 
 template <typename T>
 struct ColArgs {
@@ -554,6 +603,7 @@ struct ColArgs {
   const T* kaxis;      // |xi|^2 table of the transformed axis
   const T* kouter;     // |xi|^2 table indexed by the outer index (3D z pass), or null
   const double* mean_c;  // double mean of c (held k = 0 mode)
+  c2<T>* cstate;         // carried spectrum of c (update mode), x-spectrum layout
   double* partials;
   long long fs_src, fs_dst;  // field strides (complex elements)
   long long ls;              // stride between consecutive transform elements
@@ -561,22 +611,26 @@ struct ColArgs {
   int ncols;                 // active columns (Nx/2 + 1)
   int nyq;                   // Nx/2 (Hermitian weight 1 at columns 0 and nyq)
   int F, mode;
+  int first;  // update mode: take c^ from src field 0 (and transform it) instead of cstate
+  int f0;     // forward/inverse modes: first field transformed
   T dtM, dtMkc, dtL, dtLke, invP;
 };
 
 // Column-pass geometry.  E = 8 elements per lane (N / 8 lanes per column),
-// C consecutive columns per work-group: 32-byte row segments for the long
-// axes (N >= 512) so that a 2D grid still yields several work-groups per
-// compute unit, 128-byte segments otherwise; at least one wavefront and at
-// most 512 lanes per group.
+// C consecutive columns per work-group: a few columns on the long axes
+// (N >= 512) so that a 2D grid yields several work-groups per compute unit,
+// 128-byte row segments otherwise; at least one wavefront and at most 512
+// lanes per group.
 template <typename T, int N>
 struct ColGeom {
-  static constexpr int E = N <= 8 ? N : 8;
+  static constexpr int E = N <= 8 ? N : ((N >= 512 && sizeof(T) == 4) ? PF_COL_E_LONG_F32 : 8);
   static constexpr int TEAM = N / E;
-  static constexpr int CB = N >= 512 ? (sizeof(T) == 8 ? 2 : 4) : (sizeof(T) == 8 ? 8 : 16);
+  static constexpr int CB = N >= 512 ? (sizeof(T) == 8 ? PF_COL_CB_LONG_F64 : PF_COL_CB_LONG_F32)
+                                    : (sizeof(T) == 8 ? 8 : 16);
   static constexpr int C0 = (CB * TEAM < 64) ? 64 / TEAM : CB;
   static constexpr int C = (C0 * TEAM > 512) ? (512 / TEAM > 0 ? 512 / TEAM : 1) : C0;
   static constexpr int WG = C * TEAM;
+  static constexpr int MIN_WAVES = sizeof(T) == 4 ? PF_COL_MIN_WAVES : 1;
 };
 
 // One work-group per (column tile, outer index, field group).  Field groups:
@@ -585,8 +639,9 @@ struct ColGeom {
 // Blocks are dealt to the eight XCDs round-robin (block b runs on XCD b % 8),
 // so the logical work index is chosen to give each XCD a contiguous run of
 // tiles: tiles that share a cache line then share one L2.
-template <typename T, int N>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, ColGeom<T, N>::WG)))
+template <typename T, int N, int MODE>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, ColGeom<T, N>::WG),
+                               amdgpu_waves_per_eu(ColGeom<T, N>::MIN_WAVES)))
 col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   using G = ColGeom<T, N>;
   constexpr int E = G::E, TEAM = G::TEAM, C = G::C;
@@ -597,7 +652,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   const int rest = L / tiles;
   const int o = rest % nouter;
   const int g = rest / nouter;
-  __shared__ c2<T> lds[N * C];
+  __shared__ c2<T> lds[2 * lds_span(N) * C];  // two exchange areas (ping-pong)
   __shared__ double red[2 * (G::WG / 64 + 1)];
   const int lane = threadIdx.x;
   const int cc = lane % C;
@@ -606,6 +661,8 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   const bool active = col < a.ncols;
   const long long base = (long long)o * a.os + (active ? col : 0);
   c2<T>* my = lds + cc;
+  c2<T>* my2 = lds + lds_span(N) * C + cc;
+  int par = 0;  // exchange parity across the transforms of this work-group
 
   auto load = [&](const c2<T>* src, c2<T>* v) {
 #pragma unroll
@@ -623,49 +680,60 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   tws.load(t, a.tw, 1);
 
   c2<T> v[E];
-  if (a.mode == COL_FWD || a.mode == COL_INV) {
-    load(a.src + g * a.fs_src, v);
-    if (a.mode == COL_FWD) team_fft<T, N, E, false, C>(v, t, my, tws);
-    else team_fft<T, N, E, true, C>(v, t, my, tws);
-    store(a.dst + g * a.fs_dst, v);
-  } else if (a.mode == COL_UPDATE) {
+  if constexpr (MODE == COL_FWD || MODE == COL_INV) {
+    load(a.src + (g + a.f0) * a.fs_src, v);
+    if constexpr (MODE == COL_FWD) par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
+    else par = team_fft<T, N, E, true, C>(v, t, my, tws, my2, par);
+    store(a.dst + (g + a.f0) * a.fs_dst, v);
+  } else if constexpr (MODE == COL_UPDATE || MODE == COL_UPDATE_FIRST) {
     if (g == 0) {
-      // c: (c^ - dt M k2 g^) / (1 + dt M kappa_c k2^2); the k = 0 mode held in double
+      // c (carried spectrum, Algorithm 1): c^ <- (c^ - dt M k2 g^) / (1 + dt M kappa_c k2^2);
+      // the inverse transform gets c^ / P with the k = 0 mode held in double
       c2<T> gg[E];
-      load(a.src, v);
       load(a.src + a.fs_src, gg);
-      team_fft<T, N, E, false, C>(v, t, my, tws);
-      team_fft<T, N, E, false, C>(gg, t, my, tws);
+      par = team_fft<T, N, E, false, C>(gg, t, my, tws, my2, par);
+      if constexpr (MODE == COL_UPDATE_FIRST) {
+        load(a.src, v);
+        par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
+      } else {
+        load(a.cstate, v);
+      }
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int e = t + TEAM * m;
         const T k2 = kc + a.kaxis[e];
-        const T D = a.invP / (T(1) + a.dtMkc * k2 * k2);
+        const T D = T(1) / (T(1) + a.dtMkc * k2 * k2);
         const T sk = a.dtM * k2;
         v[m] = mk<T>((v[m].x - sk * gg[m].x) * D, (v[m].y - sk * gg[m].y) * D);
+      }
+      store(a.cstate, v);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int e = t + TEAM * m;
+        v[m] = mk<T>(v[m].x * a.invP, v[m].y * a.invP);
         if (col == 0 && o == 0 && e == 0) v[m] = mk<T>(T(*a.mean_c), T(0));
       }
-      team_fft<T, N, E, true, C>(v, t, my, tws);
+      par = team_fft<T, N, E, true, C>(v, t, my, tws, my2, par);
       store(a.dst, v);
     } else {
       // eta_g: b^ / (1 + dt L kappa_eta k2)
       load(a.src + (g + 1) * a.fs_src, v);
-      team_fft<T, N, E, false, C>(v, t, my, tws);
+      par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
         const T D = a.invP / (T(1) + a.dtLke * k2);
         v[m] = mk<T>(v[m].x * D, v[m].y * D);
       }
-      team_fft<T, N, E, true, C>(v, t, my, tws);
+      par = team_fft<T, N, E, true, C>(v, t, my, tws, my2, par);
       store(a.dst + g * a.fs_dst, v);
     }
-  } else if (a.mode == COL_ADJ) {
+  } else if constexpr (MODE == COL_ADJ) {
     if (g == 0) {
       // e_c = x/(1+x) lambda_c^ (x = dt M kappa_c k2^2), b_c = D_c k2 lambda_c^
       c2<T> bb[E];
       load(a.src, v);
-      team_fft<T, N, E, false, C>(v, t, my, tws);
+      par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
@@ -674,14 +742,14 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
         bb[m] = mk<T>(v[m].x * D * k2, v[m].y * D * k2);
         v[m] = mk<T>(v[m].x * D * x, v[m].y * D * x);
       }
-      team_fft<T, N, E, true, C>(v, t, my, tws);
+      par = team_fft<T, N, E, true, C>(v, t, my, tws, my2, par);
       store(a.dst, v);
-      team_fft<T, N, E, true, C>(bb, t, my, tws);
+      par = team_fft<T, N, E, true, C>(bb, t, my, tws, my2, par);
       store(a.dst + a.fs_dst, bb);
     } else {
       // e_g = y/(1+y) lambda_g^ (y = dt L kappa_eta k2)
       load(a.src + g * a.fs_src, v);
-      team_fft<T, N, E, false, C>(v, t, my, tws);
+      par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
@@ -689,14 +757,15 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
         const T D = a.invP * y / (T(1) + y);
         v[m] = mk<T>(v[m].x * D, v[m].y * D);
       }
-      team_fft<T, N, E, true, C>(v, t, my, tws);
+      par = team_fft<T, N, E, true, C>(v, t, my, tws, my2, par);
       store(a.dst + (g + 1) * a.fs_dst, v);
     }
   } else {  // COL_ENERGY: sum of w_kx k2 |u^|^2 of field g
+    static_assert(MODE == COL_ENERGY, "unknown column mode");
     double acc[2] = {0.0, 0.0};
     const double wcol = (col == 0 || col == a.nyq) ? 1.0 : 2.0;
     load(a.src + g * a.fs_src, v);
-    team_fft<T, N, E, false, C>(v, t, my, tws);
+    par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
     if (active) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {

@@ -52,7 +52,7 @@ struct pf_handle {
   // host tables in double: twiddles (re, im interleaved) and |xi|^2 per axis
   std::vector<double> tw[3], kt[3];
   // workspace layout (byte offsets)
-  size_t off_B, off_S, off_tw[3], off_k[3], off_part, off_scal, ws_need;
+  size_t off_B, off_S, off_C, off_tw[3], off_k[3], off_part, off_scal, ws_need;
   size_t spec_field;  // complex elements per x-spectrum field
   long long nparts;
   std::vector<unsigned char> staging;
@@ -133,6 +133,8 @@ template <typename T>
 c2<T>* specB(const pf_handle* h) { return reinterpret_cast<c2<T>*>(h->ws + h->off_B); }
 template <typename T>
 c2<T>* specS(const pf_handle* h) { return reinterpret_cast<c2<T>*>(h->ws + h->off_S); }
+template <typename T>
+c2<T>* specC(const pf_handle* h) { return reinterpret_cast<c2<T>*>(h->ws + h->off_C); }
 double* partials(const pf_handle* h) { return reinterpret_cast<double*>(h->ws + h->off_part); }
 double* scal(const pf_handle* h) { return reinterpret_cast<double*>(h->ws + h->off_scal); }
 
@@ -170,6 +172,7 @@ ColArgs<T> cargs(const pf_handle* h, double dt) {
   std::memset(&a, 0, sizeof(a));
   a.kcol = ktp<T>(h, 0);
   a.mean_c = scal(h) + SC_MEANC;
+  a.cstate = specC<T>(h);
   a.partials = partials(h);
   a.fs_src = a.fs_dst = (long long)h->spec_field;
   a.ncols = h->nxh;
@@ -229,10 +232,14 @@ pf_status reduce(pf_handle* h, int n, int width, double* out, double s0, double 
   } while (0)
 
 // k-space update between forward and inverse transforms along the strided
-// axes: 2D one column pass; 3D y-forward, z update, y-inverse.
+// axes: 2D one column pass; 3D y-forward, z update, y-inverse.  On the first
+// step of a call the spectrum of c is transformed from B (field 0) into the
+// carried state; later steps reuse the carried state and B holds only the
+// F right-hand sides in fields 1..F.
 template <typename T>
-pf_status spectral_update(pf_handle* h, double dt) {
+pf_status spectral_update(pf_handle* h, double dt, bool first) {
   ColArgs<T> a = cargs<T>(h, dt);
+  a.first = first ? 1 : 0;
   if (h->nd == 2) {
     a.src = specB<T>(h);
     a.dst = specS<T>(h);
@@ -242,8 +249,10 @@ pf_status spectral_update(pf_handle* h, double dt) {
   a.src = specB<T>(h);
   a.dst = specB<T>(h);
   a.mode = COL_FWD;
-  a.F = h->F + 1;
+  a.f0 = first ? 0 : 1;
+  a.F = first ? h->F + 1 : h->F;
   PF_TRY(col<T>(h, a, 1, nullptr));
+  a.f0 = 0;
   a.F = h->F;
   a.dst = specS<T>(h);
   a.mode = COL_UPDATE;
@@ -269,13 +278,13 @@ pf_status fs_run(pf_handle* h, double dt, long long nsteps, const T* uin, T* uou
   x.dtL = T(dt * h->L);
   x.u_in = uin;
   x.b_out = specB<T>(h);
-  x.flags = X_LOAD_REAL | X_FWD_DERIV | X_ESUM;
+  x.flags = X_LOAD_REAL | X_FWD_DERIV | X_WITH_C | X_ESUM;
   int nb = 0;
   PF_TRY(row<T>(h, x, &nb));
   PF_TRY(reduce(h, nb, 2, scal(h) + SC_FSUM, 1.0, 1.0 / double(h->P), 0, 0));
   const long long fsz = (long long)h->F * h->P;
   for (long long s = 0; s < nsteps; ++s) {
-    PF_TRY(spectral_update<T>(h, dt));
+    PF_TRY(spectral_update<T>(h, dt, s == 0));
     XArgs<T> y = xargs<T>(h);
     y.dtL = T(dt * h->L);
     y.s_in = specS<T>(h);
@@ -578,6 +587,8 @@ pf_status pf_create(const pf_config* cfg, pf_handle** out) {
   off = align256(off + size_t(h->F + 1) * h->spec_field * cbytes);
   h->off_S = off;
   off = align256(off + size_t(h->F + 1) * h->spec_field * cbytes);
+  h->off_C = off;
+  off = align256(off + h->spec_field * cbytes);
   for (int ax = 0; ax < 3; ++ax) {
     h->off_tw[ax] = off;
     off = align256(off + size_t(ns[ax]) * cbytes);

@@ -165,7 +165,8 @@ def main(argv=None):
     achieved = A / (avg[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(dom),
-            "kernel": "xpass_kernel<float,1024,4>" if dom == "row" else "col_kernel<float,1024>",
+            "kernel": ("rowpass_kernel<float,1024,4,X_FWD_DERIV,FE_PAPER> (row pass)" if dom == "row"
+                       else "col_kernel<float,1024,COL_UPDATE> (column pass)"),
             "algorithmic_bytes_per_launch": A,
             "avg_launch_us": round(avg[dom] * 1e3, 3),
             "other_kernel": {"name": "col" if dom == "row" else "row",

@@ -15,11 +15,13 @@
 // outputs back to the same registers it read (its output index equals its
 // input index), so an N = E^P transform needs P - 1 LDS exchanges.
 //
-// Twiddles come from a per-axis table W[q] = exp(-2 pi i q / Naxis) that the
-// host computes in extended precision (rounded once for float or double); a
-// length-N transform on an axis of length Naxis reads W[q * (Naxis / N)].
-// Each lane loads the few twiddles its passes need into registers once per
-// kernel, so no table load sits in the dependency chain of a pass.
+// Twiddles come from a per-axis double-precision table
+// W[q] = exp(-2 pi i q / Naxis) that the host computes in extended precision;
+// a length-N transform on an axis of length Naxis reads W[q * (Naxis / N)].
+// Each lane reads one table entry per pass and forms the other powers it
+// needs by double-precision complex multiplication, rounding once to the
+// working precision, so a kernel issues a handful of table loads per lane
+// and none sits in the dependency chain of a pass.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,6 +57,14 @@ template <typename T>
 __device__ __forceinline__ c2<T> conj(c2<T> a) { return mk<T>(a.x, -a.y); }
 template <typename T>
 __device__ __forceinline__ c2<T> scale(c2<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 dmul(double2 a, double2 b) {
+  double2 r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ c2<T> rnd(double2 a) { return mk<T>(T(a.x), T(a.y)); }
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
@@ -154,15 +164,38 @@ struct Twiddles {
   static constexpr int P = num_passes<N, E>();
   static constexpr int NT = (P - 1) * (E - 1) > 0 ? (P - 1) * (E - 1) : 1;
   c2<T> w[NT];
-  __device__ __forceinline__ void load(int t, const c2<T>* __restrict__ tw, int tws) {
+  // tw: the axis table in double; tws = Naxis / N
+  __device__ __forceinline__ void load(int t, const double2* __restrict__ tw, int tws) {
     int ns = first_radix<N, E>();
 #pragma unroll
     for (int p = 1; p < P; ++p) {
       const int k = t & (ns - 1);
       const int step = N / (ns * E);
+      const double2 w1 = tw[(k * step) * tws];
+      double2 wr = w1;
 #pragma unroll
-      for (int r = 1; r < E; ++r) w[(p - 1) * (E - 1) + (r - 1)] = tw[(r * k * step) * tws];
+      for (int r = 1; r < E; ++r) {
+        w[(p - 1) * (E - 1) + (r - 1)] = rnd<T>(wr);
+        wr = dmul(wr, w1);
+      }
       ns *= E;
+    }
+  }
+};
+
+// exp(-2 pi i k / N) for the E positions k = t + TEAM m a lane holds, from
+// the double table of length N (one per-lane entry and one common step).
+template <typename T, int N, int E>
+struct LaneTwiddles {
+  c2<T> w[E];
+  __device__ __forceinline__ void load(int t, const double2* __restrict__ tw) {
+    constexpr int TEAM = N / E;
+    const double2 step = tw[TEAM];
+    double2 cur = tw[t];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      w[m] = rnd<T>(cur);
+      cur = dmul(cur, step);
     }
   }
 };

@@ -44,6 +44,9 @@
 #ifndef PF_ROW_NW
 #define PF_ROW_NW 4  // wavefronts per row-pass work-group (0: p_max + 1)
 #endif
+#ifndef PF_COL_PINGPONG
+#define PF_COL_PINGPONG 1  // two LDS exchange areas in the column pass
+#endif
 #ifndef PF_COL_E_LONG_F32
 #define PF_COL_E_LONG_F32 8  // elements per lane, float column transforms of length >= 512
 #endif
@@ -65,7 +68,7 @@ struct XArgs {
   T* u_out;
   const c2<T>* s_in;
   c2<T>* b_out;
-  const c2<T>* twx;  // exp(-2 pi i q / Nx), q < Nx
+  const double2* twx;  // exp(-2 pi i q / Nx), q < Nx, double
   double* partials;
   long long fs_real;  // field stride of real arrays (elements)
   long long fs_spec;  // field stride of x-spectra (complex elements)
@@ -91,7 +94,7 @@ struct XGeom {
 // extension (x_j = sum_k X_k exp(+2 pi i j k / NX)).
 template <typename T, int NX, int E>
 __device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src, bool active,
-                                        int t, c2<T>* my, const c2<T>* __restrict__ twx,
+                                        int t, c2<T>* my, const LaneTwiddles<T, NX / 2, E>& lt,
                                         const Twiddles<T, NX / 2, E>& tws) {
   constexpr int NH = NX / 2;
   constexpr int TEAM = NH / E;
@@ -107,7 +110,7 @@ __device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src,
     const int k = t + TEAM * m;
     const c2<T> Y = conj<T>(my[NH - k]);
     const c2<T> s = add<T>(X[m], Y);
-    const c2<T> d = cmulc<T>(sub<T>(X[m], Y), twx[k]);  // * exp(+2 pi i k / NX)
+    const c2<T> d = cmulc<T>(sub<T>(X[m], Y), lt.w[m]);  // * exp(+2 pi i k / NX)
     v[m] = mk<T>(s.x - d.y, s.y + d.x);                 // s + i d
   }
   __syncthreads();
@@ -117,7 +120,7 @@ __device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src,
 // R2C of one row held as v[m] = (x[2k], x[2k+1]); writes X[0..NH] to dst.
 template <typename T, int NX, int E>
 __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* __restrict__ dst, bool active, int t,
-                                        c2<T>* my, const c2<T>* __restrict__ twx,
+                                        c2<T>* my, const LaneTwiddles<T, NX / 2, E>& lt,
                                         const Twiddles<T, NX / 2, E>& tws) {
   constexpr int NH = NX / 2;
   constexpr int TEAM = NH / E;
@@ -133,7 +136,7 @@ __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* __restrict__ dst, bool 
     const c2<T> s = add<T>(Z, Zc);  // 2 A_k
     const c2<T> d = sub<T>(Z, Zc);  // 2 i B_k
     const c2<T> B2 = mk<T>(d.y, -d.x);  // 2 B_k
-    const c2<T> WB = cmul<T>(B2, twx[k]);
+    const c2<T> WB = cmul<T>(B2, lt.w[m]);
     if (active) dst[k] = mk<T>(T(0.5) * (s.x + WB.x), T(0.5) * (s.y + WB.y));
     if (k == 0 && active) dst[NH] = mk<T>(T(0.5) * (s.x - B2.x), T(0.5) * (s.y - B2.y));
   }
@@ -159,6 +162,8 @@ xpass_kernel(XArgs<T> a) {
   const int p = F - 1;
   Twiddles<T, NH, E> tws;
   tws.load(t, a.twx, 2);
+  LaneTwiddles<T, NH, E> lt;  // exp(-2 pi i k / NX), k = t + TEAM m
+  lt.load(t, a.twx);
 
   c2<T> u[FB][E];
   if (a.flags & X_LOAD_REAL) {
@@ -172,7 +177,7 @@ xpass_kernel(XArgs<T> a) {
   } else {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
-      if (f < F) row_c2r<T, NX, E>(u[f], a.s_in + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
+      if (f < F) row_c2r<T, NX, E>(u[f], a.s_in + f * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
   }
 
   if ((a.flags & X_STORE_REAL) && active) {
@@ -236,15 +241,15 @@ xpass_kernel(XArgs<T> a) {
       gcv[m] = mk<T>(gcx, gcy);
     }
     if (a.flags & X_WITH_C)
-      row_r2c<T, NX, E>(u[0], a.b_out + 0 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
-    row_r2c<T, NX, E>(gcv, a.b_out + 1 * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
+      row_r2c<T, NX, E>(u[0], a.b_out + 0 * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
+    row_r2c<T, NX, E>(gcv, a.b_out + 1 * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
 #pragma unroll
     for (int i = 0; i < PMAX; ++i)
-      if (i < p) row_r2c<T, NX, E>(u[1 + i], a.b_out + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
+      if (i < p) row_r2c<T, NX, E>(u[1 + i], a.b_out + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
   } else if (a.flags & X_FWD_RAW) {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
-      if (f < F) row_r2c<T, NX, E>(u[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
+      if (f < F) row_r2c<T, NX, E>(u[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
   }
 }
 
@@ -308,6 +313,8 @@ rowpass_kernel(XArgs<T> a) {
   const int flags = FX >= 0 ? (FX | (a.flags & X_STORE_REAL)) : a.flags;
   Twiddles<T, NH, E> tws;
   tws.load(t, a.twx, 2);
+  LaneTwiddles<T, NH, E> lt;  // exp(-2 pi i k / NX), k = t + TEAM m
+  lt.load(t, a.twx);
 
   // phase 1: real rows into the row buffer
   if (flags & X_LOAD_REAL) {
@@ -340,7 +347,7 @@ rowpass_kernel(XArgs<T> a) {
           const c2<T> X = src[k];
           const c2<T> Y = conj<T>(src[NH - k]);
           const c2<T> sm = add<T>(X, Y);
-          const c2<T> d = cmulc<T>(sub<T>(X, Y), a.twx[k]);  // * exp(+2 pi i k / NX)
+          const c2<T> d = cmulc<T>(sub<T>(X, Y), lt.w[m]);  // * exp(+2 pi i k / NX)
           v[m] = mk<T>(sm.x - d.y, sm.y + d.x);
         }
         team_fft<T, NH, E, true, 1, true>(v, t, ar, tws);
@@ -439,7 +446,7 @@ rowpass_kernel(XArgs<T> a) {
           const c2<T> sm = add<T>(Z, Zc);
           const c2<T> d = sub<T>(Z, Zc);
           const c2<T> B2 = mk<T>(d.y, -d.x);
-          const c2<T> WB = cmul<T>(B2, a.twx[k]);
+          const c2<T> WB = cmul<T>(B2, lt.w[m]);
           dst[k] = mk<T>(T(0.5) * (sm.x + WB.x), T(0.5) * (sm.y + WB.y));
           if (k == 0) dst[NH] = mk<T>(T(0.5) * (sm.x - B2.x), T(0.5) * (sm.y - B2.y));
         }
@@ -472,7 +479,7 @@ struct AdjArgs {
   const T* u_np1;
   T* lam;
   c2<T>* b_out;
-  const c2<T>* twx;
+  const double2* twx;
   const double* mean_c;
   double* partials;
   long long fs_real, fs_spec;
@@ -510,14 +517,16 @@ adj_row_kernel(AdjArgs<T> a) {
   const int p = F - 1;
   Twiddles<T, G::NH, E> tws;
   tws.load(t, a.twx, 2);
+  LaneTwiddles<T, G::NH, E> lt;  // exp(-2 pi i k / NX), k = t + TEAM m
+  lt.load(t, a.twx);
 
   // w[0] = e_c, w[1..p] = e_i, bc = b_c; w is overwritten by lambda^n
   c2<T> w[FB][E], bc[E];
-  row_c2r<T, NX, E>(w[0], a.s_in + rrow * a.Sx, active, t, my, a.twx, tws);
-  row_c2r<T, NX, E>(bc, a.s_in + a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
+  row_c2r<T, NX, E>(w[0], a.s_in + rrow * a.Sx, active, t, my, lt, tws);
+  row_c2r<T, NX, E>(bc, a.s_in + a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
 #pragma unroll
   for (int i = 0; i < PMAX; ++i)
-    if (i < p) row_c2r<T, NX, E>(w[1 + i], a.s_in + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
+    if (i < p) row_c2r<T, NX, E>(w[1 + i], a.s_in + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
 
   double q[4] = {0.0, 0.0, 0.0, 0.0};
   const double cmean = *a.mean_c;
@@ -584,7 +593,7 @@ adj_row_kernel(AdjArgs<T> a) {
   if (a.do_fwd) {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
-      if (f < F) row_r2c<T, NX, E>(w[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, a.twx, tws);
+      if (f < F) row_r2c<T, NX, E>(w[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
   }
 }
 
@@ -598,7 +607,7 @@ template <typename T>
 struct ColArgs {
   const c2<T>* src;
   c2<T>* dst;
-  const c2<T>* tw;     // exp(-2 pi i q / N) for the transformed axis
+  const double2* tw;   // exp(-2 pi i q / N) for the transformed axis, double
   const T* kcol;       // |xi|^2 table indexed by the column (x frequency)
   const T* kaxis;      // |xi|^2 table of the transformed axis
   const T* kouter;     // |xi|^2 table indexed by the outer index (3D z pass), or null
@@ -652,7 +661,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   const int rest = L / tiles;
   const int o = rest % nouter;
   const int g = rest / nouter;
-  __shared__ c2<T> lds[2 * lds_span(N) * C];  // two exchange areas (ping-pong)
+  __shared__ c2<T> lds[(PF_COL_PINGPONG ? 2 : 1) * lds_span(N) * C];
   __shared__ double red[2 * (G::WG / 64 + 1)];
   const int lane = threadIdx.x;
   const int cc = lane % C;
@@ -661,7 +670,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   const bool active = col < a.ncols;
   const long long base = (long long)o * a.os + (active ? col : 0);
   c2<T>* my = lds + cc;
-  c2<T>* my2 = lds + lds_span(N) * C + cc;
+  c2<T>* my2 = PF_COL_PINGPONG ? lds + lds_span(N) * C + cc : nullptr;
   int par = 0;  // exchange parity across the transforms of this work-group
 
   auto load = [&](const c2<T>* src, c2<T>* v) {
@@ -688,20 +697,20 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   } else if constexpr (MODE == COL_UPDATE || MODE == COL_UPDATE_FIRST) {
     if (g == 0) {
       // c (carried spectrum, Algorithm 1): c^ <- (c^ - dt M k2 g^) / (1 + dt M kappa_c k2^2);
-      // the inverse transform gets c^ / P with the k = 0 mode held in double
+      // the inverse transform gets c^ / P with the k = 0 mode held in double.
+      // Both column arrays are loaded up front so their latencies overlap.
       c2<T> gg[E];
       load(a.src + a.fs_src, gg);
-      par = team_fft<T, N, E, false, C>(gg, t, my, tws, my2, par);
       if constexpr (MODE == COL_UPDATE_FIRST) {
         load(a.src, v);
-        par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
       } else {
         load(a.cstate, v);
       }
+      par = team_fft<T, N, E, false, C>(gg, t, my, tws, my2, par);
+      if constexpr (MODE == COL_UPDATE_FIRST) par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const int e = t + TEAM * m;
-        const T k2 = kc + a.kaxis[e];
+        const T k2 = kc + a.kaxis[t + TEAM * m];
         const T D = T(1) / (T(1) + a.dtMkc * k2 * k2);
         const T sk = a.dtM * k2;
         v[m] = mk<T>((v[m].x - sk * gg[m].x) * D, (v[m].y - sk * gg[m].y) * D);

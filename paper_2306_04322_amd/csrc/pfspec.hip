@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pfspec.h"
+#include "pfspec.h"
 #include "pf_kernels.h"
 #include "pf_launch.h"
 
@@ -122,8 +122,8 @@ FeParams<T> fe_params(const pf_handle* h) {
 }
 
 template <typename T>
-const c2<T>* twp(const pf_handle* h, int ax) {
-  return reinterpret_cast<const c2<T>*>(h->ws + h->off_tw[ax]);
+const double2* twp(const pf_handle* h, int ax) {
+  return reinterpret_cast<const double2*>(h->ws + h->off_tw[ax]);
 }
 template <typename T>
 const T* ktp(const pf_handle* h, int ax) {
@@ -435,11 +435,8 @@ void fill_staging(pf_handle* h) {
   h->staging.assign(h->ws_need - h->off_tw[0], 0);
   unsigned char* base = h->staging.data() - h->off_tw[0];
   for (int ax = 0; ax < 3; ++ax) {
-    c2<T>* tw = reinterpret_cast<c2<T>*>(base + h->off_tw[ax]);
-    for (size_t q = 0; q < h->tw[ax].size() / 2; ++q) {
-      tw[q].x = T(h->tw[ax][2 * q]);
-      tw[q].y = T(h->tw[ax][2 * q + 1]);
-    }
+    double* tw = reinterpret_cast<double*>(base + h->off_tw[ax]);
+    for (size_t q = 0; q < h->tw[ax].size(); ++q) tw[q] = h->tw[ax][q];
     T* kt = reinterpret_cast<T*>(base + h->off_k[ax]);
     for (size_t i = 0; i < h->kt[ax].size(); ++i) kt[i] = T(h->kt[ax][i]);
   }
@@ -589,9 +586,9 @@ pf_status pf_create(const pf_config* cfg, pf_handle** out) {
   off = align256(off + size_t(h->F + 1) * h->spec_field * cbytes);
   h->off_C = off;
   off = align256(off + h->spec_field * cbytes);
-  for (int ax = 0; ax < 3; ++ax) {
+  for (int ax = 0; ax < 3; ++ax) {  // twiddle tables are double for both precisions
     h->off_tw[ax] = off;
-    off = align256(off + size_t(ns[ax]) * cbytes);
+    off = align256(off + size_t(ns[ax]) * 2 * sizeof(double));
   }
   for (int ax = 0; ax < 3; ++ax) {
     h->off_k[ax] = off;

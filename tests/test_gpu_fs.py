@@ -151,3 +151,33 @@ def test_full_size_3d_256_z_invariant(prec):
     # every plane identical
     first = got[:, 0:1]
     assert bool((got == first).all())
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_3d_256_single_mode_closed_form(prec):
+    """3D 256^3, c + 4 eta (the 3D benchmark shape): with eta = 0 exactly the
+    c equation is linear under the paper's f_chem (df/dc = 2 rho2 (c - c_alpha)),
+    so one Fourier mode of c is multiplied per step by
+    G = (1 - dt M k2 f_cc) / (1 + dt M kappa_c k2^2), f_cc = 2 rho2, and the
+    order parameters stay exactly zero.  Checked on sampled points."""
+    torch = gpu_or_fail()
+    from paper_2306_04322_amd.pfspec import Solver
+    cfg = I.make_config(3, 256, 1.0, 4, I.PAPER_FE)
+    m = (3, 5, 7)
+    A, c0, dt, n = 0.05, 0.45, 0.1, 3
+    u = I.single_mode(cfg, [c0, 0.0, 0.0, 0.0, 0.0], A, 0, m)
+    k2 = sum((2 * np.pi * md / 256.0) ** 2 for md in m)
+    G = (1 - dt * 5.0 * k2 * 4.0) / (1 + dt * 5.0 * 3.0 * k2 * k2)
+    announce("fs full 256^3 single mode", prec)
+    s = Solver(cfg, prec)
+    s.set_fields(u)
+    s.step_fs(dt, n)
+    rng = np.random.Generator(np.random.PCG64(3))
+    idx = rng.integers(0, 256, size=(3, 2000))
+    z, y, x = (torch.as_tensor(i, device=s.device) for i in idx)
+    got = s.fields[0, z, y, x].double().cpu().numpy()
+    phase = 2 * np.pi * (m[0] * idx[2] + m[1] * idx[1] + m[2] * idx[0]) / 256.0
+    expect = c0 + A * G ** n * np.cos(phase)
+    tol = 1e-12 if prec == "f64" else 2e-6
+    assert np.max(np.abs(got - expect)) <= tol
+    assert float(s.fields[1:].abs().max()) == 0.0

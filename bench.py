@@ -158,9 +158,13 @@ def main(argv=None):
     ms = 1e3 * t / args.steps
     log("fp32 %.3f ms/step, %.3e pt-upd/s" % (ms, value))
 
-    prof = kernel_profile(s32, dt, min(args.steps, 500), torch)
-    avg = {k: (v[1] / v[0] if v[0] else 0.0) for k, v in prof.items()}
-    dom = "row" if prof["row"][1] >= prof["col"][1] else "col"
+    # each steady-state pass timed on its own, back to back between two HIP
+    # events on the library's stream (pf_time_pass)
+    from paper_2306_04322_amd import pfspec as PF
+    reps = max(50, min(args.steps, 500))
+    avg = {"row": PF.pf_time_pass(s32.h, 0, reps), "col": PF.pf_time_pass(s32.h, 1, reps)}
+    dom = "row" if avg["row"] >= avg["col"] else "col"
+    oth = "col" if dom == "row" else "row"
     A = algorithmic_bytes(cfg, "f32", dom)
     achieved = A / (avg[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -169,10 +173,10 @@ def main(argv=None):
                        else "col_kernel<float,1024,COL_UPDATE> (column pass)"),
             "algorithmic_bytes_per_launch": A,
             "avg_launch_us": round(avg[dom] * 1e3, 3),
-            "other_kernel": {"name": "col" if dom == "row" else "row",
-                             "avg_launch_us": round(avg["col" if dom == "row" else "row"] * 1e3, 3),
-                             "achieved_GBs": round(algorithmic_bytes(cfg, "f32", "col" if dom == "row" else "row")
-                                                   / (avg["col" if dom == "row" else "row"] * 1e-3) / 1e9, 1)}}
+            "launches_timed": reps,
+            "other_kernel": {"name": oth, "avg_launch_us": round(avg[oth] * 1e3, 3),
+                             "achieved_GBs": round(algorithmic_bytes(cfg, "f32", oth)
+                                                   / (avg[oth] * 1e-3) / 1e9, 1)}}
     log("roofline", roof)
 
     out = {"metric": METRIC, "value": value, "unit": "grid-pt updates/s", "n_gpus": 1,

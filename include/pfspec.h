@@ -151,6 +151,16 @@ pf_status pf_profile_enable(pf_handle* h, int32_t enable);
  *  4 = adjoint row pass): count and summed milliseconds. */
 pf_status pf_profile_read(pf_handle* h, int32_t kernel_class, int64_t* count, double* total_ms);
 
+/* Time one pass of the steady-state FS step on its own: `pass` 0 = the row
+ * pass (inverse x transform, free-energy derivative, forward x transform),
+ * 1 = the k-space update pass (the column pass in 2D; the z-update pass in
+ * 3D).  Launches it `reps` times back to back on the handle's stream
+ * between two events, after one untimed launch, and returns the average
+ * milliseconds per launch in *avg_ms (synchronises).  Reads and rewrites
+ * the step's intermediate buffers in the workspace, so call it after
+ * pf_step_fs; the bound fields are not touched.  reps >= 1. */
+pf_status pf_time_pass(pf_handle* h, int32_t pass, int32_t reps, double* avg_ms);
+
 const char* pf_status_string(pf_status s);
 const char* pf_last_error(void);
 int32_t pf_version(void);

@@ -597,6 +597,177 @@ adj_row_kernel(AdjArgs<T> a) {
   }
 }
 
+// Adjoint row pass, one wavefront per transform (the forward row pass's
+// structure and geometry).  Slots: 0 = e_c, 1 = b_c, 2 + i = e_i; the
+// pointwise phase overwrites slots 0 and 2 + i with lambda^n for the
+// forward transforms of phase 3.
+template <typename T, int NX, int PMAX>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, RGeom<T, NX, PMAX>::WG)))
+adjrow_kernel(AdjArgs<T> a) {
+  using G = RGeom<T, NX, PMAX>;
+  constexpr int NH = G::NH, E = G::E, TEAM = G::TEAM, UPW = G::UPW, ROWS = G::ROWS;
+  constexpr int NW = G::NW, SL = G::SLOTS, WG = G::WG, SC = G::SLOT_C;
+  static_assert(G::FITS, "adjoint row pass v2 does not fit this size");
+  __shared__ __align__(16) c2<T> rb[ROWS * SL * SC];
+  __shared__ double red[4 * (NW + 1)];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int unit = lane / TEAM;
+  const int t = lane - unit * TEAM;
+  const int row0 = blockIdx.x * ROWS;
+  const int F = a.F;
+  const int p = F - 1;
+  Twiddles<T, NH, E> tws;
+  tws.load(t, a.twx, 2);
+  LaneTwiddles<T, NH, E> lt;
+  lt.load(t, a.twx);
+
+  // phase 1: C2R of the F + 1 adjoint x-spectra into slots 0..F
+  {
+    const int nin = F + 1;
+    const int njobs = ROWS * nin;
+    for (int base = wave * UPW; base < njobs; base += NW * UPW) {
+      const int j = base + unit;
+      const int r = j / nin;
+      const int sl = j - r * nin;
+      if (j < njobs && row0 + r < a.rows) {
+        const c2<T>* src = a.s_in + sl * a.fs_spec + (long long)(row0 + r) * a.Sx;
+        c2<T>* ar = rb + (r * SL + sl) * SC;
+        c2<T> v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int k = t + TEAM * m;
+          const c2<T> X = src[k];
+          const c2<T> Y = conj<T>(src[NH - k]);
+          const c2<T> sm = add<T>(X, Y);
+          const c2<T> d = cmulc<T>(sub<T>(X, Y), lt.w[m]);
+          v[m] = mk<T>(sm.x - d.y, sm.y + d.x);
+        }
+        team_fft<T, NH, E, true, 1, true>(v, t, ar, tws);
+        team_sync<true>();
+#pragma unroll
+        for (int m = 0; m < E; ++m) ar[pad(t + TEAM * m)] = v[m];
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 2: Hessian-vector product, new lambda, parameter-gradient dots
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  const double cmean = *a.mean_c;
+  const int npairs = ROWS * NH;
+  for (int qi = tid; qi < npairs; qi += WG) {
+    const int r = qi / NH;
+    const int x2 = qi - r * NH;
+    const int row = row0 + r;
+    if (row < a.rows) {
+      c2<T>* pt = rb + r * SL * SC + pad(x2);
+      const long long off = (long long)row * NH + x2;
+      c2<T> un[PMAX + 1], un1[PMAX + 1], lm[PMAX + 1];
+#pragma unroll
+      for (int f = 0; f < PMAX + 1; ++f)
+        if (f < F) {
+          un[f] = reinterpret_cast<const c2<T>*>(a.u_n + f * a.fs_real)[off];
+          un1[f] = reinterpret_cast<const c2<T>*>(a.u_np1 + f * a.fs_real)[off];
+          lm[f] = reinterpret_cast<const c2<T>*>(a.lam + f * a.fs_real)[off];
+        }
+      const c2<T> ecv = pt[0];
+      const c2<T> bcv = pt[SC];
+      c2<T> ev[PMAX];
+#pragma unroll
+      for (int i = 0; i < PMAX; ++i) ev[i] = (i < p) ? pt[(2 + i) * SC] : mk<T>(T(0), T(0));
+      c2<T> nl[PMAX + 1];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        T eta[PMAX], ge[PMAX], ve[PMAX], oe[PMAX], ai[PMAX];
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i) {
+          eta[i] = (i < p) ? (h ? un[1 + i].y : un[1 + i].x) : T(0);
+          const T li = (i < p) ? (h ? lm[1 + i].y : lm[1 + i].x) : T(0);
+          const T ei = (i < p) ? (h ? ev[i].y : ev[i].x) : T(0);
+          ai[i] = li - ei;
+          ve[i] = a.dtL * ai[i];
+          ge[i] = T(0);
+          oe[i] = T(0);
+        }
+        const T c = h ? un[0].y : un[0].x;
+        const T ec = h ? ecv.y : ecv.x;
+        const T lc = h ? lm[0].y : lm[0].x;
+        const T ac = lc - ec;
+        const T b = h ? bcv.y : bcv.x;
+        T gc, oc;
+        fe_grad<T, PMAX>(a.fe, p, c, eta, gc, ge);
+        fe_hvp<T, PMAX>(a.fe, p, c, eta, a.dtM * b, ve, oc, oe);
+        const T cn1 = h ? un1[0].y : un1[0].x;
+        q[0] += double(b) * double(gc);
+        q[1] += double(ec) * (double(cn1) - cmean);
+        const T nc = ac - oc;
+        if (h) nl[0].y = nc; else nl[0].x = nc;
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i)
+          if (i < p) {
+            const T ei = h ? ev[i].y : ev[i].x;
+            const T en1 = h ? un1[1 + i].y : un1[1 + i].x;
+            q[2] += double(ai[i]) * double(ge[i]);
+            q[3] += double(ei) * double(en1);
+            const T ni = ai[i] - oe[i];
+            if (h) nl[1 + i].y = ni; else nl[1 + i].x = ni;
+          }
+      }
+      pt[0] = nl[0];
+      reinterpret_cast<c2<T>*>(a.lam)[off] = nl[0];
+#pragma unroll
+      for (int i = 0; i < PMAX; ++i)
+        if (i < p) {
+          pt[(2 + i) * SC] = nl[1 + i];
+          reinterpret_cast<c2<T>*>(a.lam + (1 + i) * a.fs_real)[off] = nl[1 + i];
+        }
+    }
+  }
+  block_sum<4>(q, red);
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.partials[4 * blockIdx.x + k] = q[k];
+  }
+  __syncthreads();
+
+  // phase 3: R2C of lambda^n (slots 0 and 2 + i) for the next adjoint step
+  if (a.do_fwd) {
+    const int njobs = ROWS * F;
+    for (int base = wave * UPW; base < njobs; base += NW * UPW) {
+      const int j = base + unit;
+      const int r = j / F;
+      const int f = j - r * F;
+      if (j < njobs && row0 + r < a.rows) {
+        c2<T>* ar = rb + (r * SL + (f == 0 ? 0 : f + 1)) * SC;
+        c2<T> v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = ar[pad(t + TEAM * m)];
+        team_sync<true>();
+        team_fft<T, NH, E, false, 1, true>(v, t, ar, tws);
+        team_sync<true>();
+#pragma unroll
+        for (int m = 0; m < E; ++m) ar[pad(t + TEAM * m)] = v[m];
+        team_sync<true>();
+        c2<T>* dst = a.b_out + f * a.fs_spec + (long long)(row0 + r) * a.Sx;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int k = t + TEAM * m;
+          const c2<T> Z = v[m];
+          const c2<T> Zc = conj<T>(ar[pad((NH - k) & (NH - 1))]);
+          const c2<T> sm = add<T>(Z, Zc);
+          const c2<T> d = sub<T>(Z, Zc);
+          const c2<T> B2 = mk<T>(d.y, -d.x);
+          const c2<T> WB = cmul<T>(B2, lt.w[m]);
+          dst[k] = mk<T>(T(0.5) * (sm.x + WB.x), T(0.5) * (sm.y + WB.y));
+          if (k == 0) dst[NH] = mk<T>(T(0.5) * (sm.x - B2.x), T(0.5) * (sm.y - B2.y));
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Column pass.
 

@@ -60,6 +60,7 @@ struct pf_handle {
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   // profiling
+  double last_dt = 0.0;  // time step of the last pf_step_fs call
   bool prof_on = false;
   std::vector<ProfRec> prof_pool;
   size_t prof_used = 0;
@@ -524,6 +525,45 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 }  // namespace
 
+namespace {
+template <typename T>
+pf_status time_pass_run(pf_handle* h, int pass, int reps, double* avg_ms) {
+  const double dt = h->last_dt > 0.0 ? h->last_dt : 0.1;
+  auto launch = [&]() -> pf_status {
+    if (pass == 0) {
+      XArgs<T> y = xargs<T>(h);
+      y.dtL = T(dt * h->L);
+      y.s_in = specS<T>(h);
+      y.b_out = specB<T>(h);
+      y.flags = X_FWD_DERIV;
+      return row<T>(h, y, nullptr);
+    }
+    ColArgs<T> a = cargs<T>(h, dt);
+    a.src = specB<T>(h);
+    a.dst = specS<T>(h);
+    a.mode = COL_UPDATE;
+    return col<T>(h, a, h->nd == 2 ? 1 : 2, nullptr);
+  };
+  PF_TRY(launch());
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(PF_ERR_HIP, "hipEventCreate failed");
+  pf_status st = PF_OK;
+  if (hipEventRecord(e0, h->stream) != hipSuccess) st = fail(PF_ERR_HIP, "hipEventRecord failed");
+  for (int i = 0; i < reps && st == PF_OK; ++i) st = launch();
+  float ms = 0.f;
+  if (st == PF_OK) {
+    if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      st = fail(PF_ERR_HIP, "event timing failed");
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == PF_OK) *avg_ms = double(ms) / reps;
+  return st;
+}
+}  // namespace
+
 extern "C" {
 
 pf_status pf_create(const pf_config* cfg, pf_handle** out) {
@@ -668,6 +708,7 @@ static pf_status check_step(pf_handle* h, double dt, int64_t nsteps) {
 
 pf_status pf_step_fs(pf_handle* h, double dt, int64_t nsteps) {
   PF_TRY(check_step(h, dt, nsteps));
+  h->last_dt = dt;
   if (h->es == 4) {
     float* u = static_cast<float*>(h->fields);
     return fs_run<float>(h, dt, nsteps, u, u, nullptr);
@@ -700,6 +741,15 @@ pf_status pf_adjoint_fs(pf_handle* h, double dt, int64_t k, const void* u_ckpt, 
                     : adjoint_run<double>(h, dt, k, static_cast<const double*>(u_ckpt),
                                           static_cast<double*>(lambda), dparams,
                                           static_cast<double*>(seg_store));
+}
+
+
+pf_status pf_time_pass(pf_handle* h, int32_t pass, int32_t reps, double* avg_ms) {
+  if (!h || !avg_ms) return fail(PF_ERR_INVALID, "handle and avg_ms must be non-NULL");
+  if (!h->ws) return fail(PF_ERR_INVALID, "pf_bind has not been called");
+  if ((pass != 0 && pass != 1) || reps < 1) return fail(PF_ERR_INVALID, "pass must be 0 or 1, reps >= 1");
+  return h->es == 4 ? time_pass_run<float>(h, pass, reps, avg_ms)
+                    : time_pass_run<double>(h, pass, reps, avg_ms);
 }
 
 pf_status pf_profile_enable(pf_handle* h, int32_t enable) {

@@ -53,6 +53,8 @@ _sig = {
     "pf_profile_enable": (ctypes.c_int, [_H, ctypes.c_int32]),
     "pf_profile_read": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]),
+    "pf_time_pass": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_double)]),
     "pf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pf_last_error": (ctypes.c_char_p, []),
     "pf_version": (ctypes.c_int32, []),
@@ -75,6 +77,12 @@ class PFError(RuntimeError):
 def _check(st, where):
     if st != PF_OK:
         raise PFError(st, where)
+
+
+def pf_time_pass(h, pass_id, reps):
+    ms = ctypes.c_double()
+    _check(_lib.pf_time_pass(h, pass_id, reps, ctypes.byref(ms)), "pf_time_pass")
+    return float(ms.value)
 
 
 def pf_status_string(status):

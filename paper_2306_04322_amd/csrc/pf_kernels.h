@@ -47,6 +47,9 @@
 #ifndef PF_COL_PINGPONG
 #define PF_COL_PINGPONG 1  // two LDS exchange areas in the column pass
 #endif
+#ifndef PF_FAST_RCP
+#define PF_FAST_RCP 1  // float k-space multipliers through the hardware reciprocal
+#endif
 #ifndef PF_COL_E_LONG_F32
 #define PF_COL_E_LONG_F32 8  // elements per lane, float column transforms of length >= 512
 #endif
@@ -61,6 +64,15 @@ enum {
   X_ESUM = 16,       // double sums of f(u) and c -> partials[block][2]
   X_WITH_C = 32      // with X_FWD_DERIV: also R2C of c -> b_out field 0
 };
+
+// 1 / x for the k-space multipliers (x >= 1).  float: the hardware
+// reciprocal (error within 1 ulp) instead of the correctly rounded division
+// sequence; double: the division.
+template <typename T>
+__device__ __forceinline__ T recip(T x) {
+  if constexpr (sizeof(T) == 4 && PF_FAST_RCP) return __builtin_amdgcn_rcpf(x);
+  else return T(1) / x;
+}
 
 template <typename T>
 struct XArgs {
@@ -818,7 +830,9 @@ struct ColGeom {
 // needs c^ and g^ together) and one per eta_i; energy: one per field.
 // Blocks are dealt to the eight XCDs round-robin (block b runs on XCD b % 8),
 // so the logical work index is chosen to give each XCD a contiguous run of
-// tiles: tiles that share a cache line then share one L2.
+// tiles: tiles that share a cache line then share one L2.  The field group
+// is the fastest-varying part of that index, so every XCD receives the same
+// mix of c groups (two arrays in and out) and eta groups (one).
 template <typename T, int N, int MODE>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, ColGeom<T, N>::WG),
                                amdgpu_waves_per_eu(ColGeom<T, N>::MIN_WAVES)))
@@ -828,10 +842,10 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   const int b = blockIdx.x;
   const int L = (b & 7) * nslots + (b >> 3);
   if (L >= tiles * nouter * ngroups) return;
-  const int tile = L % tiles;
-  const int rest = L / tiles;
-  const int o = rest % nouter;
-  const int g = rest / nouter;
+  const int g = L % ngroups;
+  const int rest = L / ngroups;
+  const int tile = rest % tiles;
+  const int o = rest / tiles;
   __shared__ c2<T> lds[(PF_COL_PINGPONG ? 2 : 1) * lds_span(N) * C];
   __shared__ double red[2 * (G::WG / 64 + 1)];
   const int lane = threadIdx.x;
@@ -839,20 +853,31 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   const int t = lane / C;
   const int col = tile * C + cc;
   const bool active = col < a.ncols;
-  const long long base = (long long)o * a.os + (active ? col : 0);
   c2<T>* my = lds + cc;
   c2<T>* my2 = PF_COL_PINGPONG ? lds + lds_span(N) * C + cc : nullptr;
   int par = 0;  // exchange parity across the transforms of this work-group
 
+  // Element t + TEAM m of this lane's column sits at a work-group-uniform
+  // 64-bit base (field, outer plane, tile, m) plus a 32-bit per-lane byte
+  // offset that is the same for every m, so the address arithmetic runs on
+  // the scalar unit.  The offset is below 2^32 for every supported shape
+  // (at most C + TEAM ls complex values).
+  const long long wg0 = (long long)o * a.os + (long long)tile * C;
+  const unsigned lbo = (unsigned(cc) + unsigned(t) * unsigned(a.ls)) * unsigned(sizeof(c2<T>));
   auto load = [&](const c2<T>* src, c2<T>* v) {
 #pragma unroll
-    for (int m = 0; m < E; ++m)
-      v[m] = active ? src[base + (long long)(t + TEAM * m) * a.ls] : mk<T>(T(0), T(0));
+    for (int m = 0; m < E; ++m) {
+      const char* pm = reinterpret_cast<const char*>(src + wg0 + (long long)m * TEAM * a.ls);
+      v[m] = active ? *reinterpret_cast<const c2<T>*>(pm + lbo) : mk<T>(T(0), T(0));
+    }
   };
   auto store = [&](c2<T>* dst, const c2<T>* v) {
     if (active) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) dst[base + (long long)(t + TEAM * m) * a.ls] = v[m];
+      for (int m = 0; m < E; ++m) {
+        char* pm = reinterpret_cast<char*>(dst + wg0 + (long long)m * TEAM * a.ls);
+        *reinterpret_cast<c2<T>*>(pm + lbo) = v[m];
+      }
     }
   };
   const T kc = a.kcol[active ? col : 0] + (a.kouter ? a.kouter[o] : T(0));
@@ -882,7 +907,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
-        const T D = T(1) / (T(1) + a.dtMkc * k2 * k2);
+        const T D = recip<T>(T(1) + a.dtMkc * k2 * k2);
         const T sk = a.dtM * k2;
         v[m] = mk<T>((v[m].x - sk * gg[m].x) * D, (v[m].y - sk * gg[m].y) * D);
       }
@@ -902,7 +927,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
-        const T D = a.invP / (T(1) + a.dtLke * k2);
+        const T D = a.invP * recip<T>(T(1) + a.dtLke * k2);
         v[m] = mk<T>(v[m].x * D, v[m].y * D);
       }
       par = team_fft<T, N, E, true, C>(v, t, my, tws, my2, par);
@@ -918,7 +943,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
         const T x = a.dtMkc * k2 * k2;
-        const T D = a.invP / (T(1) + x);
+        const T D = a.invP * recip<T>(T(1) + x);
         bb[m] = mk<T>(v[m].x * D * k2, v[m].y * D * k2);
         v[m] = mk<T>(v[m].x * D * x, v[m].y * D * x);
       }
@@ -934,7 +959,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
         const T y = a.dtLke * k2;
-        const T D = a.invP * y / (T(1) + y);
+        const T D = a.invP * y * recip<T>(T(1) + y);
         v[m] = mk<T>(v[m].x * D, v[m].y * D);
       }
       par = team_fft<T, N, E, true, C>(v, t, my, tws, my2, par);

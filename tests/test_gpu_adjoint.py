@@ -47,7 +47,7 @@ def _gpu_adjoint(cfg, prec, u0, lam_T, dt, nsteps, K):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("case", ["paper2d", "poly2d", "paper3d", "fd2"])
+@pytest.mark.parametrize("case", ["paper2d", "poly2d", "paper3d", "paper3d_cube", "fd2"])
 def test_adjoint_matches_oracle(case, prec):
     if case == "paper2d":
         cfg = _cfg(2, 32, 2)
@@ -55,6 +55,8 @@ def test_adjoint_matches_oracle(case, prec):
         cfg = _cfg(2, (16, 32), 3, I.POLY_FE)
     elif case == "paper3d":
         cfg = _cfg(3, (16, 8, 8), 4)
+    elif case == "paper3d_cube":
+        cfg = _cfg(3, 32, 2)
     else:
         cfg = _cfg(2, (32, 16), 2, kmode="fd2")
     dt, nsteps, K = (0.02, 10, 4) if case != "poly2d" else (1e-3, 10, 4)

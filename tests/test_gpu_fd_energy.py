@@ -59,7 +59,7 @@ def test_fd_shapes_parity(ndim, n, p, prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("scheme", ["fs", "fd"])
-@pytest.mark.parametrize("case", ["WO", "rand2d", "rand3d", "poly"])
+@pytest.mark.parametrize("case", ["WO", "rand2d", "rand3d", "rand3d_wide", "poly"])
 def test_energy_parity(case, scheme, prec):
     if case == "WO":
         cfg, w = I.workload_config("WO")
@@ -70,6 +70,10 @@ def test_energy_parity(case, scheme, prec):
     elif case == "rand3d":
         cfg = I.make_config(3, (16, 32, 8), 1.0, 4, I.PAPER_FE)
         u0 = I.random_ic(cfg, 5, c0=0.45)
+    elif case == "rand3d_wide":
+        # several full column tiles plus the Nyquist column on both strided axes
+        cfg = I.make_config(3, (64, 32, 32), (1.0, 0.9, 1.1), 2, I.PAPER_FE)
+        u0 = I.random_ic(cfg, 8, c0=0.45)
     else:
         cfg = I.make_config(2, 32, 1.0, 3, I.POLY_FE)
         u0 = I.random_ic(cfg, 6)

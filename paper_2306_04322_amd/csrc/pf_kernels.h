@@ -265,6 +265,41 @@ xpass_kernel(XArgs<T> a) {
   }
 }
 
+// Input half of a C2R by one wavefront team: pairs each X_k of the
+// x-spectrum row src[0..NH] with conj(X_{NH-k}) and leaves in v[m] the
+// complex sequence whose length-NH inverse FFT gives the real row as pairs
+// (x[2k], x[2k+1]), k = t + TEAM m.  `lt` holds exp(-2 pi i k / (2 NH)).
+// float rows of Nx <= 512 (several teams per wavefront): the row is read
+// once from global memory and the mirrored values come from the team's LDS
+// area `ar`, which saves the registers of a second set of loads (one more
+// wavefront per SIMD on 256-point rows); otherwise both reads come from
+// global memory (measured faster where occupancy does not change).
+template <typename T, int NH, int E>
+__device__ __forceinline__ void wave_c2r_pre(c2<T>* v, const c2<T>* __restrict__ src, c2<T>* ar,
+                                             int t, const LaneTwiddles<T, NH, E>& lt) {
+  constexpr int TEAM = NH / E;
+  constexpr bool STAGE = sizeof(T) == 4 && TEAM < 64;
+  c2<T> X[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) X[m] = src[t + TEAM * m];
+  if constexpr (STAGE) {
+    const c2<T> xn = src[t == 0 ? NH : 0];
+#pragma unroll
+    for (int m = 0; m < E; ++m) ar[pad(t + TEAM * m)] = X[m];
+    if (t == 0) ar[pad(NH)] = xn;
+    team_sync<true>();
+  }
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = t + TEAM * m;
+    const c2<T> Y = conj<T>(STAGE ? ar[pad(NH - k)] : src[NH - k]);
+    const c2<T> sm = add<T>(X[m], Y);
+    const c2<T> d = cmulc<T>(sub<T>(X[m], Y), lt.w[m]);  // * exp(+2 pi i k / NX)
+    v[m] = mk<T>(sm.x - d.y, sm.y + d.x);
+  }
+  if constexpr (STAGE) team_sync<true>();
+}
+
 // ---------------------------------------------------------------------------
 // Row pass, one wavefront per transform.  The work-group owns ROWS rows and
 // stages them in an LDS row buffer of F + 1 real rows each (slot 0 = c,
@@ -353,15 +388,7 @@ rowpass_kernel(XArgs<T> a) {
         const c2<T>* src = a.s_in + f * a.fs_spec + (long long)(row0 + r) * a.Sx;
         c2<T>* ar = rb + (r * SL + (f == 0 ? 0 : f + 1)) * SC;
         c2<T> v[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-          const int k = t + TEAM * m;
-          const c2<T> X = src[k];
-          const c2<T> Y = conj<T>(src[NH - k]);
-          const c2<T> sm = add<T>(X, Y);
-          const c2<T> d = cmulc<T>(sub<T>(X, Y), lt.w[m]);  // * exp(+2 pi i k / NX)
-          v[m] = mk<T>(sm.x - d.y, sm.y + d.x);
-        }
+        wave_c2r_pre<T, NH, E>(v, src, ar, t, lt);
         team_fft<T, NH, E, true, 1, true>(v, t, ar, tws);
         team_sync<true>();
 #pragma unroll
@@ -647,15 +674,7 @@ adjrow_kernel(AdjArgs<T> a) {
         const c2<T>* src = a.s_in + sl * a.fs_spec + (long long)(row0 + r) * a.Sx;
         c2<T>* ar = rb + (r * SL + sl) * SC;
         c2<T> v[E];
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-          const int k = t + TEAM * m;
-          const c2<T> X = src[k];
-          const c2<T> Y = conj<T>(src[NH - k]);
-          const c2<T> sm = add<T>(X, Y);
-          const c2<T> d = cmulc<T>(sub<T>(X, Y), lt.w[m]);
-          v[m] = mk<T>(sm.x - d.y, sm.y + d.x);
-        }
+        wave_c2r_pre<T, NH, E>(v, src, ar, t, lt);
         team_fft<T, NH, E, true, 1, true>(v, t, ar, tws);
         team_sync<true>();
 #pragma unroll
@@ -825,14 +844,22 @@ struct ColGeom {
   static constexpr int MIN_WAVES = sizeof(T) == 4 ? PF_COL_MIN_WAVES : 1;
 };
 
+// Work order of the column pass (see col_kernel): per-XCD chunks of tiles
+// for float and for the 3D passes, field group fastest for 2D double (the
+// faster choice for each on MI355X).
+template <typename T>
+__host__ __device__ inline bool col_chunked(int nouter) {
+  return sizeof(T) == 4 || nouter > 1;
+}
+
 // One work-group per (column tile, outer index, field group).  Field groups:
 // forward/inverse: one per field; update and adjoint: the c group (which
 // needs c^ and g^ together) and one per eta_i; energy: one per field.
 // Blocks are dealt to the eight XCDs round-robin (block b runs on XCD b % 8),
 // so the logical work index is chosen to give each XCD a contiguous run of
-// tiles: tiles that share a cache line then share one L2.  The field group
-// is the fastest-varying part of that index, so every XCD receives the same
-// mix of c groups (two arrays in and out) and eta groups (one).
+// tiles (tiles that share a cache line then share one L2) and the same mix
+// of c groups (two arrays in and out) and eta groups (one); col_chunked
+// selects between the two orders that do this.
 template <typename T, int N, int MODE>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, ColGeom<T, N>::WG),
                                amdgpu_waves_per_eu(ColGeom<T, N>::MIN_WAVES)))
@@ -840,12 +867,29 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   using G = ColGeom<T, N>;
   constexpr int E = G::E, TEAM = G::TEAM, C = G::C;
   const int b = blockIdx.x;
-  const int L = (b & 7) * nslots + (b >> 3);
-  if (L >= tiles * nouter * ngroups) return;
-  const int g = L % ngroups;
-  const int rest = L / ngroups;
-  const int tile = rest % tiles;
-  const int o = rest / tiles;
+  int L, g, tile, o;
+  if (col_chunked<T>(nouter)) {
+    // units u = (outer, tile), tile fastest, cut into eight contiguous
+    // chunks of `nslots` units; XCD x takes chunk x for every field group,
+    // group by group, so neighbouring tiles of one field run back to back on
+    // one L2 and every XCD gets the same mix of c and eta groups.
+    const int nu = tiles * nouter;
+    const int j = b >> 3;
+    g = j / nslots;
+    const int u = (b & 7) * nslots + (j - g * nslots);
+    if (g >= ngroups || u >= nu) return;
+    L = g * nu + u;  // dense record index
+    tile = u % tiles;
+    o = u / tiles;
+  } else {
+    // field group fastest over a contiguous run of work items per XCD
+    L = (b & 7) * nslots + (b >> 3);
+    if (L >= tiles * nouter * ngroups) return;
+    g = L % ngroups;
+    const int rest = L / ngroups;
+    tile = rest % tiles;
+    o = rest / tiles;
+  }
   __shared__ c2<T> lds[(PF_COL_PINGPONG ? 2 : 1) * lds_span(N) * C];
   __shared__ double red[2 * (G::WG / 64 + 1)];
   const int lane = threadIdx.x;

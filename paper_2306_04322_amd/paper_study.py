@@ -19,12 +19,14 @@ fields are not available):
   2. coarser grids take those fields at every k-th point; finer grids get
      their band-limited (Fourier) interpolation, an input-preparation step
      done once on the host;
-  3. FS runs (pf_step_fs) t = 1 -> t_end for each grid and time step, FD
-     runs where affordable, timed with device synchronisation;
+  3. runs t = 1 -> t_end for each method (FS, the FS-FD variants of
+     Eq. (17), (18) and FD with the Table 1 time steps), grid and time
+     step, timed with device synchronisation; FD only where affordable (its
+     Table 1 step at 1024^2 and 2048^2 means 10^7 - 10^9 steps);
   4. E_c, E_eta of each run against the finest/smallest-dt FS run, on the
      coarser run's grid points.
-The full protocol (n up to 2048, t_end = 100, dt = 1e-4) takes several
-minutes of GPU time; --quick shrinks it to seconds.
+The full protocol (n up to 2048, t_end = 100, dt = 1e-4) takes minutes of
+GPU time per method; --quick shrinks it to seconds.
 """
 
 import argparse
@@ -45,13 +47,16 @@ def paper_config(n, kmode="spectral"):
 
 
 def fd_stable_dt(n, safety=0.7):
-    """Linear FD bound for f_chem at eta = 0 (f_cc = 2 rho2, f_ee = 2 w), times
-    `safety` (Table 1's steps are 0.72-0.79 of it)."""
+    """Linear FD bound for f_chem, times `safety` (Table 1's steps are 0.72 -
+    0.92 of it).  Curvatures: f_cc = 2 rho2 = 4 everywhere; f_eta_i eta_i is
+    at most about 2 w + 4 w alpha + 2 = 24 on states with sum_j eta_j^2 <= 1
+    (the double-well part, the alpha coupling and the c-dependent h''
+    term), far above its value 2 w at eta = 0."""
     dx = DOMAIN / n
     q = 8.0 / dx ** 2
     M, kc, L, ke = 5.0, 3.0, 5.0, 3.0
     ch = 2.0 / (M * q * (4.0 + kc * q))
-    ac = 2.0 / (L * (2.0 + ke * q))
+    ac = 2.0 / (L * (24.0 + ke * q))
     return safety * min(ch, ac)
 
 
@@ -81,7 +86,19 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run(grids, dts, t0, t_end, fd_grids, prec="f64", n_per=1024, log=_log):
+# Table 1: FD time step per grid (the FS methods use 1e-4, 1e-3, 5e-3).
+TABLE1_FD_DT = {128: 8.138e-3, 256: 5.086e-4, 512: 3.560e-5, 1024: 2.225e-6, 2048: 1.490e-7}
+METHODS = {"fs": ("fs", "spectral"), "fs-fd2": ("fs", "fd2"), "fs-fd4": ("fs", "fd4"),
+           "fd": ("fd", "spectral")}
+
+
+def run(grids, dts, t0, t_end, methods, fd_grids, prec="f64", n_per=1024, log=_log,
+        sink=None, save_ref=None, ref_file=None):
+    """Run the study; `sink(results)` (optional) is called after every run so
+    partial results survive an interrupted session.  The reference fields
+    that the errors need (c and sum_i eta_i of the finest/smallest-dt FS run,
+    in float32) can be written to `save_ref` (.npz) and read back from
+    `ref_file` by a later session instead of being recomputed."""
     import torch
     from .pfspec import Solver
 
@@ -104,11 +121,11 @@ def run(grids, dts, t0, t_end, fd_grids, prec="f64", n_per=1024, log=_log):
     u1 = s.get_fields()
     del s
     results = {"periodisation": {"grid": n_per, "dt": dtp, "steps": nper, "wall_s": tper},
-               "runs": []}
+               "precision": prec, "t0": t0, "t_end": t_end, "runs": []}
 
-    def evolve(n, dt, scheme):
+    def evolve(n, dt, scheme, kmode):
         u = resample(u1, n)
-        cfg = paper_config(n)
+        cfg = paper_config(n, kmode)
         sv = Solver(cfg, prec)
         sv.set_fields(u)
         nsteps = int(round((t_end - t0) / dt))
@@ -126,7 +143,7 @@ def run(grids, dts, t0, t_end, fd_grids, prec="f64", n_per=1024, log=_log):
             if time.perf_counter() - last > 30.0:
                 torch.cuda.synchronize()
                 last = time.perf_counter()
-                log("  %s %d^2: %d / %d steps" % (scheme, n, done, nsteps))
+                log("  %s/%s %d^2: %d / %d steps" % (scheme, kmode, n, done, nsteps))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
         out = sv.get_fields()
@@ -135,25 +152,43 @@ def run(grids, dts, t0, t_end, fd_grids, prec="f64", n_per=1024, log=_log):
         return out, wall, nsteps, E
 
     ref_dt = min(dts)
-    ref, wall, nst, E = evolve(nfine, ref_dt, "fs")
-    log("reference FS %d^2 dt=%g: %d steps, %.1f s" % (nfine, ref_dt, nst, wall))
-    results["reference"] = {"grid": nfine, "dt": ref_dt, "steps": nst, "wall_s": wall,
-                            "energy": E.tolist()}
-    cases = [(n, dt, "fs") for n in sorted(grids) for dt in sorted(dts)
-             if not (n == nfine and dt == ref_dt)]
-    cases += [(n, fd_stable_dt(n), "fd") for n in sorted(fd_grids)]
-    for n, dt, scheme in cases:
-        out, wall, nst, E = evolve(n, dt, scheme)
+    if ref_file:
+        z = np.load(ref_file)
+        ref_c, ref_e = z["c"].astype(np.float64), z["eta"].astype(np.float64)
+        assert ref_c.shape == (nfine, nfine) and float(z["dt"]) == ref_dt
+        results["reference"] = json.loads(str(z["meta"]))
+        log("reference read from %s" % ref_file)
+    else:
+        ref, wall, nst, E = evolve(nfine, ref_dt, "fs", "spectral")
+        ref_c, ref_e = ref[0], np.sum(ref[1:], axis=0)
+        log("reference FS %d^2 dt=%g: %d steps, %.1f s" % (nfine, ref_dt, nst, wall))
+        results["reference"] = {"method": "fs", "grid": nfine, "dt": ref_dt, "steps": nst,
+                                "wall_s": wall, "energy": E.tolist()}
+        if save_ref:
+            np.savez(save_ref, c=ref_c.astype(np.float32), eta=ref_e.astype(np.float32),
+                     dt=ref_dt, meta=json.dumps(results["reference"]))
+    cases = []
+    for m in methods:
+        scheme, kmode = METHODS[m]
+        if scheme == "fs":
+            cases += [(m, n, dt) for n in sorted(grids) for dt in sorted(dts)
+                      if not (m == "fs" and n == nfine and dt == ref_dt)]
+        else:
+            cases += [(m, n, TABLE1_FD_DT.get(n, fd_stable_dt(n))) for n in sorted(fd_grids)]
+    for m, n, dt in cases:
+        scheme, kmode = METHODS[m]
+        out, wall, nst, E = evolve(n, dt, scheme, kmode)
         k = nfine // n
-        r = ref[:, ::k, ::k]
-        ec = e_phi(r[0], out[0])
-        ee = e_phi(np.sum(r[1:], axis=0), np.sum(out[1:], axis=0))
-        rec = {"scheme": scheme, "grid": n, "dt": dt, "steps": nst, "wall_s": wall,
+        ec = e_phi(ref_c[::k, ::k], out[0])
+        ee = e_phi(ref_e[::k, ::k], np.sum(out[1:], axis=0))
+        rec = {"method": m, "grid": n, "dt": dt, "steps": nst, "wall_s": wall,
                "s_per_step_per_point": wall / nst / n ** 2, "E_c_percent": 100 * ec,
                "E_eta_percent": 100 * ee, "energy": E.tolist()}
         results["runs"].append(rec)
-        log("%s %4d^2 dt=%.3e steps=%8d wall=%7.2fs E_c=%.3e%% E_eta=%.3e%%"
-            % (scheme, n, dt, nst, wall, 100 * ec, 100 * ee))
+        log("%-6s %4d^2 dt=%.3e steps=%8d wall=%7.2fs E_c=%.3e%% E_eta=%.3e%%"
+            % (m, n, dt, nst, wall, 100 * ec, 100 * ee))
+        if sink:
+            sink(results)
     return results
 
 
@@ -162,18 +197,36 @@ def main(argv=None):
     ap.add_argument("--quick", action="store_true", help="small grids and short times")
     ap.add_argument("--out", default=None)
     ap.add_argument("--prec", default="f64")
+    ap.add_argument("--methods", default="fs,fd", help="comma list of fs, fs-fd2, fs-fd4, fd")
+    ap.add_argument("--grids", default="128,256,512,1024,2048")
+    ap.add_argument("--dts", default="1e-4,1e-3,5e-3")
+    ap.add_argument("--fd-grids", default="128,256,512")
+    ap.add_argument("--t-end", type=float, default=100.0)
+    ap.add_argument("--save-ref", default=None, help="write the reference fields (.npz)")
+    ap.add_argument("--ref", default=None, help="read the reference fields (.npz)")
     args = ap.parse_args(argv)
+    methods = [m for m in args.methods.split(",") if m]
+    for m in methods:
+        if m not in METHODS:
+            ap.error("unknown method %r" % m)
+
+    def sink(res):
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write(json.dumps(res, indent=1))
+
     if args.quick:
-        res = run([64, 128, 256], [1e-3, 5e-3], 1.0, 3.0, [64, 128], args.prec)
+        res = run([64, 128, 256], [1e-3, 5e-3], 1.0, 3.0, methods, [64, 128], args.prec,
+                  sink=sink, save_ref=args.save_ref, ref_file=args.ref)
     else:
-        res = run([128, 256, 512, 1024, 2048], [1e-4, 1e-3, 5e-3], 1.0, 100.0, [128, 256],
-                  args.prec)
-    txt = json.dumps(res, indent=1)
-    if args.out:
-        with open(args.out, "w") as fh:
-            fh.write(txt)
-    else:
-        print(txt)
+        grids = [int(x) for x in args.grids.split(",")]
+        dts = [float(x) for x in args.dts.split(",")]
+        fdg = [int(x) for x in args.fd_grids.split(",") if x]
+        res = run(grids, dts, 1.0, args.t_end, methods, fdg, args.prec, sink=sink,
+                  save_ref=args.save_ref, ref_file=args.ref)
+    sink(res)
+    if not args.out:
+        print(json.dumps(res, indent=1))
     return 0
 
 

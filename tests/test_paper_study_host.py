@@ -1,0 +1,40 @@
+"""Host-side pieces of the paper-study driver: resampling between grids,
+the Eq. (22) error and the Table 1 FD steps against the linear FD bound."""
+
+import numpy as np
+
+from oracle import stability as ost
+from paper_2306_04322_amd import paper_study as PS
+
+
+def test_resample_coarsens_by_subsampling():
+    u = np.random.default_rng(0).random((3, 16, 16))
+    v = PS.resample(u, 4)
+    assert np.array_equal(v, u[:, ::4, ::4])
+
+
+def test_resample_refines_band_limited_fields_exactly():
+    m, n = 16, 64
+    x = np.arange(m) / m
+    X = np.arange(n) / n
+    f = lambda a, b: 0.3 + np.cos(2 * np.pi * 3 * a)[None, :] * np.sin(2 * np.pi * 5 * b)[:, None]
+    u = f(x, x)[None]
+    v = PS.resample(u, n)
+    assert np.max(np.abs(v[0] - f(X, X))) < 1e-12
+    # and coarsening the refined field gives the original back
+    assert np.max(np.abs(PS.resample(v, m) - u)) < 1e-12
+
+
+def test_error_measure_eq22():
+    a = np.ones((8, 8))
+    assert PS.e_phi(a, a) == 0.0
+    assert abs(PS.e_phi(a, 1.1 * a) - 0.01) < 1e-15
+
+
+def test_table1_fd_steps_are_below_the_linear_fd_bound():
+    for n, dt in PS.TABLE1_FD_DT.items():
+        bound = PS.fd_stable_dt(n, safety=1.0)
+        assert dt <= bound, (n, dt, bound)
+        dx = PS.DOMAIN / n
+        # f_chem at c = c_alpha, eta = 0: f_cc = 2 rho2 = 4, f_eta = 2 w = 2
+        assert dt <= ost.fd_bound(5.0, 3.0, 5.0, 3.0, 4.0, 2.0, (dx, dx)), (n, dt)

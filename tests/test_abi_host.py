@@ -110,5 +110,9 @@ def test_workspace_and_segment_sizes(prec, es):
             P.pf_energy(h, 0)
         with pytest.raises(P.PFError):
             P.pf_set_params(h, 1.0, -1.0, 1.0, 1.0)
+        for pass_id, reps in ((0, 10), (1, 10), (2, 10), (0, 0)):
+            with pytest.raises(P.PFError) as ei:
+                P.pf_time_pass(h, pass_id, reps)
+            assert ei.value.status == P.PF_ERR_INVALID
     finally:
         P.pf_destroy(h)

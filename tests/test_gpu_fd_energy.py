@@ -42,7 +42,10 @@ def test_fd_workload_parity(prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("ndim,n,p", [(2, (32, 8), 1), (2, (16, 64), 4), (3, (16, 8, 32), 4),
-                                      (3, (8, 8, 8), 8)])
+                                      (3, (8, 8, 8), 8),
+                                      # tiled kernels (planes of at least 64 x 16 points)
+                                      (2, (64, 16), 1), (2, (128, 32), 2), (2, (256, 64), 8),
+                                      (3, (64, 16, 8), 4), (3, (128, 32, 8), 3)])
 def test_fd_shapes_parity(ndim, n, p, prec):
     dx = (1.0, 0.8, 1.2)[:ndim]
     cfg = I.make_config(ndim, n, dx, p, I.PAPER_FE)
@@ -111,3 +114,19 @@ def test_energy_reports_nonfinite():
     with pytest.raises(PFError) as ei:
         s.energy("fd")
     assert ei.value.status == PF_ERR_NONFINITE
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fd_full_size_2d_1024(prec):
+    """2D 1024^2, c + 4 eta, in the launch configuration the benchmark times:
+    two FD steps compared element by element with the oracle."""
+    cfg, w = I.workload_config("W2")
+    u0 = I.workload_ic(cfg, w)
+    if prec == "f32":
+        u0 = fp32_rounded(u0)
+    announce("fd full 1024^2", prec)
+    s = _solver(cfg, prec, u0)
+    s.step_fd(w["dt_fd"], 2)
+    got = s.get_fields()
+    ref = ofd.fd_run(u0, cfg, w["dt_fd"], 2)
+    assert max_rel(rel_l2(got, ref)) <= (1e-13 if prec == "f64" else 1e-6)

@@ -181,3 +181,30 @@ def test_full_size_3d_256_single_mode_closed_form(prec):
     tol = 1e-12 if prec == "f64" else 2e-6
     assert np.max(np.abs(got - expect)) <= tol
     assert float(s.fields[1:].abs().max()) == 0.0
+
+
+def test_time_pass_leaves_fields_and_reports_positive_time():
+    """pf_time_pass reruns one steady-state pass on the step's intermediate
+    buffers: the bound fields stay as they are and the next step is the
+    same as without it."""
+    torch = gpu_or_fail()
+    from paper_2306_04322_amd.pfspec import PFError, Solver, pf_time_pass
+    cfg = I.make_config(2, (128, 64), 1.0, 4, I.PAPER_FE)
+    u0 = I.random_ic(cfg, seed=21)
+    announce("time pass")
+    a, b = Solver(cfg, "f64"), Solver(cfg, "f64")
+    for s in (a, b):
+        s.set_fields(u0)
+        s.step_fs(0.05, 3)
+    before = a.fields.clone()
+    for pass_id in (0, 1):
+        assert pf_time_pass(a.h, pass_id, 5) > 0.0
+    torch.cuda.synchronize()
+    assert bool((a.fields == before).all())
+    # every pf_step_fs call re-derives its carried spectra from the fields
+    a.step_fs(0.05, 2)
+    b.step_fs(0.05, 2)
+    torch.cuda.synchronize()
+    assert bool((a.fields == b.fields).all())
+    with pytest.raises(PFError):
+        pf_time_pass(a.h, 3, 5)

@@ -844,22 +844,27 @@ struct ColGeom {
   static constexpr int MIN_WAVES = sizeof(T) == 4 ? PF_COL_MIN_WAVES : 1;
 };
 
-// Work order of the column pass (see col_kernel): per-XCD chunks of tiles
-// for float and for the 3D passes, field group fastest for 2D double (the
-// faster choice for each on MI355X).
+// Work order of the column pass (see col_kernel), the faster choice for
+// each case on MI355X: 0 = field group fastest over a contiguous run of
+// items per XCD (2D double), 1 = per-XCD chunks of tiles (2D float),
+// 2 = outer rows dealt to the XCDs round-robin (3D passes).
+#ifndef PF_COL_ORDER3D
+#define PF_COL_ORDER3D 2
+#endif
 template <typename T>
-__host__ __device__ inline bool col_chunked(int nouter) {
-  return sizeof(T) == 4 || nouter > 1;
+__host__ __device__ inline int col_order(int nouter) {
+  return nouter > 1 ? PF_COL_ORDER3D : (sizeof(T) == 4 ? 1 : 0);
 }
 
 // One work-group per (column tile, outer index, field group).  Field groups:
 // forward/inverse: one per field; update and adjoint: the c group (which
 // needs c^ and g^ together) and one per eta_i; energy: one per field.
 // Blocks are dealt to the eight XCDs round-robin (block b runs on XCD b % 8),
-// so the logical work index is chosen to give each XCD a contiguous run of
-// tiles (tiles that share a cache line then share one L2) and the same mix
-// of c groups (two arrays in and out) and eta groups (one); col_chunked
-// selects between the two orders that do this.
+// so the logical work index is chosen to give each XCD the same mix of c
+// groups (two arrays in and out) and eta groups (one), with neighbouring
+// tiles of a field on one L2 (2D: tiles share cache lines) or the XCDs
+// moving through neighbouring rows of each plane together (3D: HBM
+// locality); col_order selects the order.
 template <typename T, int N, int MODE>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, ColGeom<T, N>::WG),
                                amdgpu_waves_per_eu(ColGeom<T, N>::MIN_WAVES)))
@@ -868,7 +873,22 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   constexpr int E = G::E, TEAM = G::TEAM, C = G::C;
   const int b = blockIdx.x;
   int L, g, tile, o;
-  if (col_chunked<T>(nouter)) {
+  const int order = col_order<T>(nouter);
+  if (order == 2) {
+    // outer row o on XCD o % 8, rows of one XCD in increasing order, field
+    // group by group: at any time the XCDs stream through neighbouring rows
+    // of each plane (one contiguous region per plane rather than eight)
+    const int nu = tiles * nouter;
+    const int rpx = (nouter + 7) / 8;
+    const int j = b >> 3;
+    g = j / nslots;
+    const int jj = j - g * nslots;
+    const int r = jj / tiles;
+    tile = jj - r * tiles;
+    o = r * 8 + (b & 7);
+    if (g >= ngroups || o >= nouter || r >= rpx) return;
+    L = g * nu + o * tiles + tile;  // dense record index
+  } else if (order == 1) {
     // units u = (outer, tile), tile fastest, cut into eight contiguous
     // chunks of `nslots` units; XCD x takes chunk x for every field group,
     // group by group, so neighbouring tiles of one field run back to back on

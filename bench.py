@@ -206,6 +206,19 @@ def main(argv=None):
 
     if not args.no_extras:
         extras = {}
+        # the paper's timing protocol: six repetitions of a batch of steps,
+        # mean and minimum time per step (FP32 headline workload)
+        sb = Solver(cfg, "f32")
+        sb.set_fields(u0)
+        sb.step_fs(dt, 50)
+        reps_ms = []
+        for _ in range(6):
+            tb = time_fs(sb, dt, 200, 0, torch)
+            reps_ms.append(1e3 * tb / 200)
+        extras["fs_2d_1024_f32_6x200"] = {"mean_ms_per_step": sum(reps_ms) / 6,
+                                          "min_ms_per_step": min(reps_ms),
+                                          "max_ms_per_step": max(reps_ms)}
+        del sb
         s64 = Solver(cfg, "f64")
         s64.set_fields(u0)
         n64 = min(args.steps, 1000)
@@ -279,6 +292,38 @@ def main(argv=None):
                                         "adjoint_ms_per_step_incl_recompute": 1e3 * ta,
                                         "adjoint_over_forward": ta / tf}
         del s4, seg, lam, ck
+        torch.cuda.empty_cache()
+        # 3D adjoint: 128^3, c + 4 eta, FP32, segments of K = 100 steps; device
+        # memory of a forward-only run against the adjoint's segment store
+        cfg5, w5 = I.workload_config("W5")
+        u5 = I.workload_ic(cfg5, w5)
+        torch.cuda.reset_peak_memory_stats()
+        base_mem = torch.cuda.memory_allocated()
+        s5 = Solver(cfg5, "f32")
+        s5.set_fields(u5)
+        K5 = w5["K"]
+        tf5 = time_fs(s5, w5["dt_fs"], K5, 10, torch) / K5
+        fwd_peak = torch.cuda.max_memory_allocated() - base_mem
+        ck5 = s5.fields.clone()
+        seg5 = s5.segment_store(K5)
+        lam5 = torch.randn_like(ck5)
+        s5.adjoint_fs(w5["dt_fs"], K5, ck5, lam5, seg5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s5.adjoint_fs(w5["dt_fs"], K5, ck5, lam5, seg5)
+        torch.cuda.synchronize()
+        ta5 = (time.perf_counter() - t0) / K5
+        adj_peak = torch.cuda.max_memory_allocated() - base_mem
+        nseg = w5["steps"] // K5
+        field_bytes = ck5.numel() * ck5.element_size()
+        extras["adjoint_3d_128_f32"] = {
+            "forward_ms_per_step": 1e3 * tf5, "adjoint_ms_per_step_incl_recompute": 1e3 * ta5,
+            "adjoint_over_forward": ta5 / tf5,
+            "forward_only_device_bytes": int(fwd_peak),
+            "one_segment_device_bytes": int(adj_peak),
+            "full_run_device_bytes": int(adj_peak + (nseg - 1) * field_bytes),
+            "steps": w5["steps"], "K": K5}
+        del s5, seg5, lam5, ck5
         torch.cuda.empty_cache()
         extras["paper_reference"] = {
             "hardware": "GeForce RTX 2080 Ti (4352 CUDA cores, 11 GB), CUDA 10.1, FP64, "

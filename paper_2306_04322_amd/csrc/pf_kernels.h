@@ -313,15 +313,19 @@ __device__ __forceinline__ void wave_c2r_pre(c2<T>* v, const c2<T>* __restrict__
 // wavefront-local, so only the two phase boundaries synchronise the
 // work-group.  Used when a transform fits one wavefront (Nx <= 2048) and
 // the row buffer fits LDS; otherwise xpass_kernel above.
-template <typename T, int NX, int PMAX>
+// SM selects the form for grids with few rows: one row per work-group and
+// just enough wavefronts for its F transforms, which spreads a small grid
+// over more compute units than 1024-point work-groups would.
+template <typename T, int NX, int PMAX, bool SM = false>
 struct RGeom {
   static constexpr int NH = NX / 2;
   static constexpr int E = NH >= 512 ? (NH / 64 < 16 ? NH / 64 : 16) : (NH < 8 ? NH : 8);
   static constexpr int TEAM = NH / E;
   static constexpr bool WAVE_OK = TEAM <= 64;
   static constexpr int UPW = WAVE_OK ? 64 / TEAM : 1;  // transforms per wavefront
-  static constexpr int ROWS = NX >= 1024 ? 1 : 1024 / NX;
-  static constexpr int NW = PF_ROW_NW > 0 ? PF_ROW_NW : PMAX + 1;  // one transform per wave and phase when F = PMAX + 1
+  static constexpr int ROWS = (SM || NX >= 1024) ? 1 : 1024 / NX;
+  static constexpr int NW = SM ? (PMAX + UPW) / UPW  // ceil((PMAX + 1) / UPW)
+                               : (PF_ROW_NW > 0 ? PF_ROW_NW : PMAX + 1);
   static constexpr int WG = 64 * NW;
   static constexpr int SLOTS = PMAX + 2;
   static constexpr int SLOT_C = lds_span(NH);  // complex values per slot (padded layout)
@@ -335,11 +339,11 @@ struct RGeom {
 // steady-state step gets a lean instantiation); FX = -1 reads them from the
 // arguments.  FEK >= 0
 // fixes the free-energy kind and requires p = PMAX.
-template <typename T, int NX, int PMAX, int FX, int FEK = -1>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, RGeom<T, NX, PMAX>::WG),
-                               amdgpu_waves_per_eu(FX >= 0 ? RGeom<T, NX, PMAX>::MIN_WAVES : 1)))
+template <typename T, int NX, int PMAX, int FX, int FEK = -1, bool SM = false>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, RGeom<T, NX, PMAX, SM>::WG),
+                               amdgpu_waves_per_eu(FX >= 0 ? RGeom<T, NX, PMAX, SM>::MIN_WAVES : 1)))
 rowpass_kernel(XArgs<T> a) {
-  using G = RGeom<T, NX, PMAX>;
+  using G = RGeom<T, NX, PMAX, SM>;
   constexpr int NH = G::NH, E = G::E, TEAM = G::TEAM, UPW = G::UPW, ROWS = G::ROWS;
   constexpr int NW = G::NW, SL = G::SLOTS, WG = G::WG, SC = G::SLOT_C;
   static_assert(G::FITS, "row pass v2 does not fit this size");

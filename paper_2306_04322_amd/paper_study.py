@@ -92,23 +92,15 @@ METHODS = {"fs": ("fs", "spectral"), "fs-fd2": ("fs", "fd2"), "fs-fd4": ("fs", "
            "fd": ("fd", "spectral")}
 
 
-def run(grids, dts, t0, t_end, methods, fd_grids, prec="f64", n_per=1024, log=_log,
-        sink=None, save_ref=None, ref_file=None):
-    """Run the study; `sink(results)` (optional) is called after every run so
-    partial results survive an interrupted session.  The reference fields
-    that the errors need (c and sum_i eta_i of the finest/smallest-dt FS run,
-    in float32) can be written to `save_ref` (.npz) and read back from
-    `ref_file` by a later session instead of being recomputed."""
+def periodised_ic(n_per, t0, prec="f64", log=_log):
+    """Sec. 2.1: the Eq. (4)-(5) fields evolved by FD on an n_per^2 grid of the
+    200 x 200 box from t = 0 to t0 (periodic from then on)."""
     import torch
     from .pfspec import Solver
 
-    nfine = max(grids)
-    n_per = min(n_per, nfine)
     cfg_f = paper_config(n_per)
-    u_ic = I.paper_ic_2d(cfg_f)
-    # 1. periodisation by FD, t = 0 -> t0
     s = Solver(cfg_f, prec)
-    s.set_fields(u_ic)
+    s.set_fields(I.paper_ic_2d(cfg_f))
     dtp = fd_stable_dt(n_per)
     nper = int(np.ceil(t0 / dtp))
     dtp = t0 / nper
@@ -120,8 +112,22 @@ def run(grids, dts, t0, t_end, methods, fd_grids, prec="f64", n_per=1024, log=_l
     tper = time.perf_counter() - t
     u1 = s.get_fields()
     del s
-    results = {"periodisation": {"grid": n_per, "dt": dtp, "steps": nper, "wall_s": tper},
-               "precision": prec, "t0": t0, "t_end": t_end, "runs": []}
+    return u1, {"grid": n_per, "dt": dtp, "steps": nper, "wall_s": tper}
+
+
+def run(grids, dts, t0, t_end, methods, fd_grids, prec="f64", n_per=1024, log=_log,
+        sink=None, save_ref=None, ref_file=None):
+    """Run the study; `sink(results)` (optional) is called after every run so
+    partial results survive an interrupted session.  The reference fields
+    that the errors need (c and sum_i eta_i of the finest/smallest-dt FS run,
+    in float32) can be written to `save_ref` (.npz) and read back from
+    `ref_file` by a later session instead of being recomputed."""
+    import torch
+    from .pfspec import Solver
+
+    nfine = max(grids)
+    u1, per = periodised_ic(min(n_per, nfine), t0, prec, log)
+    results = {"periodisation": per, "precision": prec, "t0": t0, "t_end": t_end, "runs": []}
 
     def evolve(n, dt, scheme, kmode):
         u = resample(u1, n)
@@ -192,6 +198,85 @@ def run(grids, dts, t0, t_end, methods, fd_grids, prec="f64", n_per=1024, log=_l
     return results
 
 
+# Sec. 2.1, 3D: a cube of edge 100; Table 2 time steps.
+DOMAIN3D = 100.0
+TABLE2_FD_DT = {16: 4.06e-2, 32: 2.54e-2, 64: 3.17e-3, 128: 7.94e-5, 256: 9.93e-6}
+TABLE2_FS_DT = 5e-3
+
+
+def paper_config_3d(n, kmode="spectral"):
+    """The 3D case on an n^3 grid of the 100^3 box."""
+    return I.make_config(3, n, DOMAIN3D / n, 4, I.PAPER_FE, kmode)
+
+
+def extrude_3d(u2, n, c0=0.5):
+    """Eq. (6): the order parameters of the 3D case from the 2D fields u2
+    ([F, m, m] on the 200 x 200 box) as
+        eta_i(x, y, z) = 0.5 {1 + tanh[atanh(2 eta_i^2D(2x, 2y) - 1)
+                                       - ((z - l_z / 2) / 5)^4]},
+    on an n^3 grid of the 100^3 box (x = j * 100 / n); c = c0 everywhere.
+    (2x, 2y) falls on every (m / n)-th 2D grid point.  2 eta^2D - 1 is kept
+    inside (-1, 1) by 1e-12 so that atanh stays finite where a relaxed 2D
+    field sits at 0 or 1 to rounding."""
+    p = u2.shape[0] - 1
+    e2 = resample(u2[1:], n)                                # eta^2D(2x, 2y), [p, n, n]
+    a = np.arctanh(np.clip(2.0 * e2 - 1.0, -1.0 + 1e-12, 1.0 - 1e-12))
+    z = np.arange(n) * (DOMAIN3D / n)
+    dz4 = ((z - DOMAIN3D / 2) / 5.0) ** 4                   # [n]
+    u = np.empty((p + 1, n, n, n))
+    u[0] = c0
+    u[1:] = 0.5 * (1.0 + np.tanh(a[:, None, :, :] - dz4[None, :, None, None]))
+    return u
+
+
+def run3d(grids, t0, t_end, methods, fd_grids, prec="f64", n_per=1024, log=_log, sink=None):
+    """Table 2: wall time from t = t0 to t_end of the 3D case per grid and
+    method (FS methods at dt = 5e-3, FD at the Table 2 step)."""
+    import torch
+    from .pfspec import Solver
+
+    u1, per = periodised_ic(n_per, t0, prec, log)
+    results = {"periodisation": per, "precision": prec, "t0": t0, "t_end": t_end, "runs3d": []}
+    cases = []
+    for m in methods:
+        scheme, kmode = METHODS[m]
+        if scheme == "fs":
+            cases += [(m, n, TABLE2_FS_DT) for n in sorted(grids)]
+        else:
+            cases += [(m, n, TABLE2_FD_DT[n]) for n in sorted(fd_grids)]
+    for m, n, dt in cases:
+        scheme, kmode = METHODS[m]
+        sv = Solver(paper_config_3d(n, kmode), prec)
+        sv.set_fields(extrude_3d(u1, n))
+        nsteps = int(round((t_end - t0) / dt))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        done, last, chunk = 0, t, 20000
+        while done < nsteps:
+            k = min(chunk, nsteps - done)
+            if scheme == "fs":
+                sv.step_fs(dt, k)
+            else:
+                sv.step_fd(dt, k)
+            done += k
+            if time.perf_counter() - last > 30.0:
+                torch.cuda.synchronize()
+                last = time.perf_counter()
+                log("  %s %d^3: %d / %d steps" % (m, n, done, nsteps))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        E = sv.energy(scheme)
+        del sv
+        rec = {"method": m, "grid": n, "dt": dt, "steps": nsteps, "wall_s": wall,
+               "s_per_step_per_point": wall / nsteps / n ** 3, "energy": E.tolist()}
+        results["runs3d"].append(rec)
+        log("%-6s %4d^3 dt=%.3e steps=%8d wall=%7.2fs %.3e s/step/point E=%.6g"
+            % (m, n, dt, nsteps, wall, rec["s_per_step_per_point"], E[0]))
+        if sink:
+            sink(results)
+    return results
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="small grids and short times")
@@ -204,6 +289,9 @@ def main(argv=None):
     ap.add_argument("--t-end", type=float, default=100.0)
     ap.add_argument("--save-ref", default=None, help="write the reference fields (.npz)")
     ap.add_argument("--ref", default=None, help="read the reference fields (.npz)")
+    ap.add_argument("--study3d", action="store_true", help="the Table 2 3D timing study")
+    ap.add_argument("--grids3d", default="16,32,64,128,256")
+    ap.add_argument("--fd-grids3d", default="16,32,64,128")
     args = ap.parse_args(argv)
     methods = [m for m in args.methods.split(",") if m]
     for m in methods:
@@ -215,7 +303,14 @@ def main(argv=None):
             with open(args.out, "w") as fh:
                 fh.write(json.dumps(res, indent=1))
 
-    if args.quick:
+    if args.study3d:
+        g3 = [int(x) for x in args.grids3d.split(",")]
+        f3 = [int(x) for x in args.fd_grids3d.split(",") if x]
+        if args.quick:
+            res = run3d([16, 32], 1.0, 2.0, methods, [16, 32], args.prec, n_per=256, sink=sink)
+        else:
+            res = run3d(g3, 1.0, args.t_end, methods, f3, args.prec, sink=sink)
+    elif args.quick:
         res = run([64, 128, 256], [1e-3, 5e-3], 1.0, 3.0, methods, [64, 128], args.prec,
                   sink=sink, save_ref=args.save_ref, ref_file=args.ref)
     else:

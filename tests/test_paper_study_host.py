@@ -38,3 +38,28 @@ def test_table1_fd_steps_are_below_the_linear_fd_bound():
         dx = PS.DOMAIN / n
         # f_chem at c = c_alpha, eta = 0: f_cc = 2 rho2 = 4, f_eta = 2 w = 2
         assert dt <= ost.fd_bound(5.0, 3.0, 5.0, 3.0, 4.0, 2.0, (dx, dx)), (n, dt)
+
+
+def test_extrude_3d_eq6():
+    """Eq. (6): the 3D order parameters equal the 2D field at (2x, 2y) on the
+    mid-plane z = l_z / 2, vanish far from it, and are symmetric about it;
+    c is the constant c_0."""
+    rng = np.random.default_rng(3)
+    m, n = 64, 16
+    u2 = np.concatenate([np.full((1, m, m), 0.5), rng.uniform(0.01, 0.99, (4, m, m))])
+    u3 = PS.extrude_3d(u2, n, c0=0.5)
+    assert u3.shape == (5, n, n, n)
+    assert np.all(u3[0] == 0.5)
+    e2 = u2[1:, ::m // n, ::m // n]
+    assert np.max(np.abs(u3[1:, n // 2] - e2)) < 1e-12      # z = l_z / 2
+    assert np.max(u3[1:, 0]) < 1e-12                          # |z - l_z / 2| = 50
+    for k in range(1, n // 2):
+        assert np.max(np.abs(u3[1:, n // 2 + k] - u3[1:, n // 2 - k])) < 1e-15
+    # away from the mid-plane the field only decreases
+    assert np.all(u3[1:, n // 2 + 1] <= u3[1:, n // 2] + 1e-15)
+
+
+def test_table2_fd_steps_are_below_the_linear_3d_fd_bound():
+    for n, dt in PS.TABLE2_FD_DT.items():
+        dx = PS.DOMAIN3D / n
+        assert dt <= ost.fd_bound(5.0, 3.0, 5.0, 3.0, 4.0, 2.0, (dx, dx, dx)), (n, dt)

@@ -89,21 +89,30 @@ def cpu_baseline(cfg, u0, dt, budget_s=20.0):
     P = int(np.prod(u0.shape[1:]))
     steps = 0
     u = u0
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
-    t0 = time.perf_counter()
-    while True:
-        u = ofs.fs_run(u, cfg, dt, 1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 50:
-            break
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    # the calling thread runs the oracle pinned to one of the host cores it
+    # may use; the affinity is restored afterwards
+    allowed = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {allowed[0]})
+    try:
+        r0 = resource.getrusage(resource.RUSAGE_THREAD)
+        t0 = time.perf_counter()
+        while True:
+            u = ofs.fs_run(u, cfg, dt, 1)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or steps >= 50:
+                break
+        r1 = resource.getrusage(resource.RUSAGE_THREAD)
+    finally:
+        os.sched_setaffinity(0, set(allowed))
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
     cores = max(1, int(round(cpu / el)))
     return {"value": P * steps / el, "unit": "grid-pt updates/s", "cores": cores,
             "kind": "oracle",
             "sample": "%d FS step(s) of the 2D 1024x1024, F=5 workload (FP64 NumPy oracle, own "
-                      "radix-2 FFT), %.1f s wall, %.1f s CPU" % (steps, el, cpu)}
+                      "radix-2 FFT), %.1f s wall, %.1f s CPU, thread pinned to core %d of %d "
+                      "allowed (%d on the host)" % (steps, el, cpu, allowed[0], len(allowed),
+                                                  os.cpu_count())}
 
 
 def traffic_from_profile(kind):

@@ -75,7 +75,26 @@ def build(jobs=None, verbose=True, defines=(), out=None):
     os.replace(tmp, lib)
     if verbose:
         print("built", lib)
+    if out is None:
+        build_example(verbose)
     return lib
+
+
+EXAMPLE_SRC = os.path.join(PKG, "examples", "fs_example.cpp")
+EXAMPLE_BIN = os.path.join(PKG, "examples", "fs_example")
+
+
+def build_example(verbose=True):
+    """The C-ABI example program (host code only), linked against the
+    in-tree library and finding it at run time next to itself."""
+    cmd = [hipcc(), "-O2", "-std=c++17", "-I" + os.path.join(ROOT, "include"), EXAMPLE_SRC,
+           "-L" + PKG, "-lpfspec", "-Wl,-rpath,$ORIGIN/..", "-o", EXAMPLE_BIN]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("example build failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    if verbose:
+        print("built", EXAMPLE_BIN)
+    return EXAMPLE_BIN
 
 
 def main(argv=None):

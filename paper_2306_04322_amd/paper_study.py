@@ -233,7 +233,7 @@ def run3d(grids, t0, t_end, methods, fd_grids, prec="f64", n_per=1024, log=_log,
     """Table 2: wall time from t = t0 to t_end of the 3D case per grid and
     method (FS methods at dt = 5e-3, FD at the Table 2 step)."""
     import torch
-    from .pfspec import Solver
+    from .pfspec import PF_ERR_NONFINITE, PFError, Solver
 
     u1, per = periodised_ic(n_per, t0, prec, log)
     results = {"periodisation": per, "precision": prec, "t0": t0, "t_end": t_end, "runs3d": []}
@@ -265,13 +265,24 @@ def run3d(grids, t0, t_end, methods, fd_grids, prec="f64", n_per=1024, log=_log,
                 log("  %s %d^3: %d / %d steps" % (m, n, done, nsteps))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
-        E = sv.energy(scheme)
+        # Table 2's FD steps on 16^3 and 32^3 exceed the explicit stability
+        # limit where the order-parameter coupling stiffens f (Sec. 3 uses
+        # these cases for timing only): the time is kept, a non-finite final
+        # state is recorded as such.
+        try:
+            E = sv.energy(scheme).tolist()
+        except PFError as err:
+            if err.status != PF_ERR_NONFINITE:
+                raise
+            E = None
         del sv
         rec = {"method": m, "grid": n, "dt": dt, "steps": nsteps, "wall_s": wall,
-               "s_per_step_per_point": wall / nsteps / n ** 3, "energy": E.tolist()}
+               "s_per_step_per_point": wall / nsteps / n ** 3, "energy": E,
+               "finite": E is not None}
         results["runs3d"].append(rec)
-        log("%-6s %4d^3 dt=%.3e steps=%8d wall=%7.2fs %.3e s/step/point E=%.6g"
-            % (m, n, dt, nsteps, wall, rec["s_per_step_per_point"], E[0]))
+        log("%-6s %4d^3 dt=%.3e steps=%8d wall=%7.2fs %.3e s/step/point E=%s"
+            % (m, n, dt, nsteps, wall, rec["s_per_step_per_point"],
+               "%.6g" % E[0] if E else "non-finite"))
         if sink:
             sink(results)
     return results

@@ -8,11 +8,14 @@
 //                                            to the 128-byte row stride Sx
 // A "row" is one (z, y) line along x; rows = Ny * Nz.
 //
-// Row pass (xpass_kernel): one team of lanes per row transforms along the
-// contiguous x axis.  Depending on `flags` it loads real rows or inverse-
-// transforms x-spectra back to real rows (C2R), optionally stores the real
-// rows, evaluates the free-energy derivative and forward-transforms (R2C)
-// the right-hand-side combinations, and accumulates double-precision sums.
+// Row pass: transforms along the contiguous x axis.  Depending on `flags`
+// it loads real rows or inverse-transforms x-spectra back to real rows
+// (C2R), optionally stores the real rows, evaluates the free-energy
+// derivative and forward-transforms (R2C) the right-hand-side combinations,
+// and accumulates double-precision sums.  rowpass_kernel (one wavefront
+// per transform, rows staged in LDS) is the main form; xpass_kernel (one
+// team of lanes per row, registers only) covers the shapes whose row
+// buffer does not fit LDS (Nx = 4096, double Nx = 2048).
 //
 // Column pass (col_kernel): transforms along a strided axis (y, or z in
 // 3D) for a tile of C consecutive x-spectrum columns.  Lanes are laid out

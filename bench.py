@@ -69,6 +69,26 @@ def time_fs(solver, dt, steps, warmup, torch):
     return time.perf_counter() - t0
 
 
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+    """Device copy rate in GB/s (bytes read + bytes written per second) of a
+    buffer four times the size of the last-level cache, with torch's copy
+    kernel timed by events on torch's current stream."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def kernel_profile(solver, dt, steps, torch):
     from paper_2306_04322_amd import pfspec as P
     P.pf_profile_enable(solver.h, True)
@@ -123,8 +143,8 @@ def traffic_from_profile(kind):
         return None
     try:
         rec = json.load(open(path))
-        from paper_2306_04322_amd.build import source_digest
-        if rec.get("source_digest") != source_digest():
+        from paper_2306_04322_amd.build import fs_kernel_digest
+        if rec.get("kernel_digest") != fs_kernel_digest():
             return None
         return rec.get(kind, {}).get("bytes_per_launch")
     except Exception:
@@ -186,6 +206,9 @@ def main(argv=None):
             "other_kernel": {"name": oth, "avg_launch_us": round(avg[oth] * 1e3, 3),
                              "achieved_GBs": round(algorithmic_bytes(cfg, "f32", oth)
                                                    / (avg[oth] * 1e-3) / 1e9, 1)}}
+    cbw = copy_bandwidth(torch, dev)
+    roof["copy_GBs"] = round(cbw, 1)
+    roof["frac_of_copy"] = round(achieved / cbw, 4)
     log("roofline", roof)
 
     out = {"metric": METRIC, "value": value, "unit": "grid-pt updates/s", "n_gpus": 1,

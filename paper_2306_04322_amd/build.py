@@ -29,16 +29,30 @@ CFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-fno-gpu-rdc"
           "-I" + os.path.join(ROOT, "include"), "-Wno-unused-result"]
 
 
-def source_digest():
-    """sha256 over the HIP sources and headers (identifies a kernel build)."""
+# The files the FP32 FS row and column kernels are compiled from.
+FS_F32_KERNEL_SOURCES = ["pf_fe.h", "pf_fft.h", "pf_kernels.h", "pf_launch.h",
+                         "k_row.inc", "k_row_f32.hip", "k_col.inc", "k_col_f32.hip"]
+
+
+def source_digest(names=None):
+    """sha256 over the named HIP sources (default: every source and header) and
+    the compile flags other than include paths (which name the checkout's
+    location); identifies the build of the kernels they define."""
     import hashlib
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h", ".inc")):
-            h.update(name.encode())
-            with open(os.path.join(CSRC, name), "rb") as fh:
-                h.update(fh.read())
+    h = hashlib.sha256(" ".join(f for f in CFLAGS if not f.startswith("-I")).encode())
+    if names is None:
+        names = [n for n in os.listdir(CSRC) if n.endswith((".hip", ".h", ".inc"))]
+    for name in sorted(names):
+        h.update(name.encode())
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def fs_kernel_digest():
+    """Digest of the FP32 FS row and column kernels alone: counter figures
+    taken on them stay valid while other kernels change."""
+    return source_digest(FS_F32_KERNEL_SOURCES)
 
 
 def hipcc():

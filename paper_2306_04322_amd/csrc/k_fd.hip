@@ -2,15 +2,21 @@
 // 7-point periodic Laplacian, every right-hand side at time t) and the
 // forward-difference free-energy sums.
 //
-// One thread per grid point, x fastest, so the centre and x-neighbour loads
-// of a wavefront are contiguous and the y/z neighbours are the same rows
-// shifted (served from cache).  Periodic wrap uses power-of-two masks
-// instead of ghost layers.
+// The two step kernels give each thread V consecutive points along x, read
+// as one vector of up to 16 bytes (V = 4 float or 2 double on large grids,
+// fewer on small ones): each field's centre values and its y / z neighbours
+// arrive as one vector load each, the x neighbours inside the vector come
+// from registers and only the two at its ends are extra scalar loads, so a
+// field costs 5 (2D) or 7 (3D) loads per V points instead of per point.
+// The y and z neighbours are rows that neighbouring work-groups also read;
+// on grids whose neighbour rows or planes fit in L2, each XCD takes a
+// contiguous band of the grid so those re-reads stay in its own L2.  The
+// energy kernel keeps one thread per point.
+// Periodic wrap uses power-of-two masks instead of ghost layers.
 #include "pf_kernels.h"
 #include "pf_launch.h"
 
 namespace pf {
-
 
 struct Nb {
   long long xm, xp, ym, yp, zm, zp;
@@ -39,47 +45,145 @@ __device__ __forceinline__ Nb neighbours(const FdArgs<T>& a, long long i) {
   return n;
 }
 
-template <typename T>
-__device__ __forceinline__ T lap(const T* __restrict__ v, long long i, const Nb& n,
-                                 const FdArgs<T>& a) {
-  const T c = v[i];
-  T r = (v[n.xp] - T(2) * c + v[n.xm]) * a.ix2 + (v[n.yp] - T(2) * c + v[n.ym]) * a.iy2;
-  if (a.ndim == 3) r += (v[n.zp] - T(2) * c + v[n.zm]) * a.iz2;
-  return r;
+// V consecutive points of one row, loaded and stored as one aligned vector
+// (V * sizeof(T) <= 16 bytes).
+template <typename T, int V>
+struct alignas(sizeof(T) * V) FdVec {
+  T v[V];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ FdVec<T, V> ld_vec(const T* __restrict__ p) {
+  return *reinterpret_cast<const FdVec<T, V>*>(p);
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void st_vec(T* p, const T* v) {
+  FdVec<T, V> w;
+#pragma unroll
+  for (int k = 0; k < V; ++k) w.v[k] = v[k];
+  *reinterpret_cast<FdVec<T, V>*>(p) = w;
+}
+
+// Neighbour offsets of the vector starting at point i0 (x0 = i0 mod nx, a
+// multiple of V): the y and z neighbour vectors and the two x neighbours
+// just outside the vector.
+struct NbV {
+  long long ym, yp, zm, zp, xl, xr;
+};
+
+template <typename T, int V>
+__device__ __forceinline__ NbV neighbours_vec(const FdArgs<T>& a, long long i0) {
+  const int x0 = int(i0 & (a.nx - 1));
+  const int y = int((i0 >> a.lx) & (a.ny - 1));
+  const int z = int(i0 >> (a.lx + a.ly));
+  const long long row = i0 - x0;
+  const long long plane = (long long)a.nx * a.ny;
+  const long long zoff = (long long)z * plane;
+  NbV n;
+  n.xl = row + ((x0 - 1) & (a.nx - 1));
+  n.xr = row + ((x0 + V) & (a.nx - 1));
+  n.ym = zoff + (long long)((y - 1) & (a.ny - 1)) * a.nx + x0;
+  n.yp = zoff + (long long)((y + 1) & (a.ny - 1)) * a.nx + x0;
+  if (a.ndim == 3) {
+    const long long rest = (long long)y * a.nx + x0;
+    n.zm = (long long)((z - 1) & (a.nz - 1)) * plane + rest;
+    n.zp = (long long)((z + 1) & (a.nz - 1)) * plane + rest;
+  } else {
+    n.zm = n.zp = i0;
+  }
+  return n;
+}
+
+// Laplacian of field v at the V points of the vector (centre values cv),
+// in the same operation order as the per-point form.
+template <typename T, int V>
+__device__ __forceinline__ void lap_vec(const T* __restrict__ v, const FdVec<T, V>& cv, const NbV& n,
+                                        const FdArgs<T>& a, T* out) {
+  const FdVec<T, V> ym = ld_vec<T, V>(v + n.ym), yp = ld_vec<T, V>(v + n.yp);
+  const T xl = v[n.xl], xr = v[n.xr];
+  FdVec<T, V> zm, zp;
+  if (a.ndim == 3) {
+    zm = ld_vec<T, V>(v + n.zm);
+    zp = ld_vec<T, V>(v + n.zp);
+  }
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    const T c = cv.v[k];
+    const T left = k == 0 ? xl : cv.v[k - 1];
+    const T right = k == V - 1 ? xr : cv.v[k + 1];
+    T r = (right - T(2) * c + left) * a.ix2 + (yp.v[k] - T(2) * c + ym.v[k]) * a.iy2;
+    if (a.ndim == 3) r += (zp.v[k] - T(2) * c + zm.v[k]) * a.iz2;
+    out[k] = r;
+  }
+}
+
+// First point of this thread's vector.  Work-groups are dealt to the eight
+// XCDs round-robin.  With `bands` set (the launch then rounds the group count
+// up to a multiple of 8) XCD x instead takes the x-th contiguous eighth of
+// the grid, so the neighbour rows or planes a group reads were mostly
+// brought into that XCD's L2 by its neighbouring groups.
+template <int V>
+__device__ __forceinline__ long long fd_first_point(int bands) {
+  unsigned b = blockIdx.x;
+  if (bands) b = (b & 7u) * (gridDim.x >> 3) + (b >> 3);
+  return ((long long)b * blockDim.x + threadIdx.x) * V;
 }
 
 // mu = df/dc - kappa_c lap(c);  eta_i' = eta_i - dt L (df/deta_i - kappa_eta lap(eta_i))
-template <typename T, int PMAX>
-__global__ void __launch_bounds__(256) fd_mu_kernel(FdArgs<T> a) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.P) return;
-  const Nb n = neighbours(a, i);
+template <typename T, int PMAX, int V>
+__global__ void __launch_bounds__(256) fd_mu_kernel(FdArgs<T> a, int bands) {
+  const long long i0 = fd_first_point<V>(bands);
+  if (i0 >= a.P) return;
+  const NbV n = neighbours_vec<T, V>(a, i0);
   const int p = a.F - 1;
-  T eta[PMAX], ge[PMAX];
+  const FdVec<T, V> cc = ld_vec<T, V>(a.in + i0);
+  FdVec<T, V> ce[PMAX];
 #pragma unroll
-  for (int j = 0; j < PMAX; ++j) {
-    eta[j] = (j < p) ? a.in[(j + 1) * a.P + i] : T(0);
-    ge[j] = T(0);
+  for (int j = 0; j < PMAX; ++j)
+    if (j < p) ce[j] = ld_vec<T, V>(a.in + (j + 1) * a.P + i0);
+  T gc[V], ge[PMAX][V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    T eta[PMAX], g[PMAX];
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+      eta[j] = (j < p) ? ce[j].v[k] : T(0);
+      g[j] = T(0);
+    }
+    fe_grad<T, PMAX>(a.fe, p, cc.v[k], eta, gc[k], g);
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) ge[j][k] = g[j];
   }
-  const T c = a.in[i];
-  T gc;
-  fe_grad<T, PMAX>(a.fe, p, c, eta, gc, ge);
-  a.mu[i] = gc - a.kc * lap(a.in, i, n, a);
+  T l[V], o[V];
+  lap_vec<T, V>(a.in, cc, n, a, l);
+#pragma unroll
+  for (int k = 0; k < V; ++k) o[k] = gc[k] - a.kc * l[k];
+  st_vec<T, V>(a.mu + i0, o);
 #pragma unroll
   for (int j = 0; j < PMAX; ++j)
     if (j < p) {
       const T* e = a.in + (j + 1) * a.P;
-      a.out[(j + 1) * a.P + i] = eta[j] - a.dtL * (ge[j] - a.ke * lap(e, i, n, a));
+      lap_vec<T, V>(e, ce[j], n, a, l);
+#pragma unroll
+      for (int k = 0; k < V; ++k) o[k] = ce[j].v[k] - a.dtL * (ge[j][k] - a.ke * l[k]);
+      st_vec<T, V>(a.out + (j + 1) * a.P + i0, o);
     }
 }
 
 // c' = c + dt M lap(mu)
-template <typename T>
-__global__ void __launch_bounds__(256) fd_c_kernel(FdArgs<T> a) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.P) return;
-  const Nb n = neighbours(a, i);
-  a.out[i] = a.in[i] + a.dtM * lap(a.mu, i, n, a);
+template <typename T, int V>
+__global__ void __launch_bounds__(256) fd_c_kernel(FdArgs<T> a, int bands) {
+  const long long i0 = fd_first_point<V>(bands);
+  if (i0 >= a.P) return;
+  const NbV n = neighbours_vec<T, V>(a, i0);
+  const FdVec<T, V> cm = ld_vec<T, V>(a.mu + i0);
+  const FdVec<T, V> c = ld_vec<T, V>(a.in + i0);
+  T l[V], o[V];
+  lap_vec<T, V>(a.mu, cm, n, a, l);
+#pragma unroll
+  for (int k = 0; k < V; ++k) o[k] = c.v[k] + a.dtM * l[k];
+  st_vec<T, V>(a.out + i0, o);
 }
 
 // partials[block] = {sum f(u), sum_d (dc/dx_d)^2, sum_i sum_d (deta_i/dx_d)^2, sum c}
@@ -118,12 +222,49 @@ __global__ void __launch_bounds__(256) fd_energy_kernel(FdArgs<T> a) {
   }
 }
 
+// Points per thread of the two step kernels: the widest vector (16 bytes at
+// most) that still leaves 512 work-groups of 256 threads, so small grids
+// keep enough waves in flight to hide load latency.
+template <typename T>
+static int fd_vec_width(long long P) {
+  for (int v = 16 / int(sizeof(T)); v > 1; v /= 2)
+    if (P / (256LL * v) >= 512) return v;
+  return 1;
+}
+
+// XCD bands pay while the three neighbour rows (2D) or planes (3D) of all F
+// fields fit in half of one XCD's 4 MiB L2; beyond that (3D 256^3) the plain
+// round-robin order, which sweeps the whole GPU through the grid together
+// and shares the neighbour planes through the last-level cache, is faster.
+template <typename T>
+static int fd_bands(const FdArgs<T>& a) {
+  const long long span = (a.ndim == 3 ? (long long)a.nx * a.ny : (long long)a.nx) * sizeof(T);
+  return 3LL * a.F * span <= (2LL << 20) ? 1 : 0;
+}
+
+template <typename T, int PMAX, int V>
+static int fd_go_v(int which, const FdArgs<T>& a, hipStream_t s) {
+  const long long nv = a.P / V;  // nx >= 8 is a multiple of V
+  const int bands = fd_bands(a);
+  int grid = int((nv + 255) / 256);
+  if (bands) grid = (grid + 7) / 8 * 8;
+  if (which == 0) hipLaunchKernelGGL((fd_mu_kernel<T, PMAX, V>), dim3(grid), dim3(256), 0, s, a, bands);
+  else hipLaunchKernelGGL((fd_c_kernel<T, V>), dim3(grid), dim3(256), 0, s, a, bands);
+  return grid;
+}
+
 template <typename T, int PMAX>
 static int fd_go(int which, const FdArgs<T>& a, hipStream_t s) {
+  if (which < 2) {
+    const int v = fd_vec_width<T>(a.P);
+    if constexpr (sizeof(T) == 4) {
+      if (v == 4) return fd_go_v<T, PMAX, 4>(which, a, s);
+    }
+    if (v == 2) return fd_go_v<T, PMAX, 2>(which, a, s);
+    return fd_go_v<T, PMAX, 1>(which, a, s);
+  }
   const int grid = int((a.P + 255) / 256);
-  if (which == 0) hipLaunchKernelGGL((fd_mu_kernel<T, PMAX>), dim3(grid), dim3(256), 0, s, a);
-  else if (which == 1) hipLaunchKernelGGL((fd_c_kernel<T>), dim3(grid), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((fd_energy_kernel<T, PMAX>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((fd_energy_kernel<T, PMAX>), dim3(grid), dim3(256), 0, s, a);
   return grid;
 }
 

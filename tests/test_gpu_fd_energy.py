@@ -43,9 +43,13 @@ def test_fd_workload_parity(prec):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("ndim,n,p", [(2, (32, 8), 1), (2, (16, 64), 4), (3, (16, 8, 32), 4),
                                       (3, (8, 8, 8), 8),
-                                      # tiled kernels (planes of at least 64 x 16 points)
                                       (2, (64, 16), 1), (2, (128, 32), 2), (2, (256, 64), 8),
-                                      (3, (64, 16, 8), 4), (3, (128, 32, 8), 3)])
+                                      (3, (64, 16, 8), 4), (3, (128, 32, 8), 3),
+                                      # two points per thread, XCD bands
+                                      (2, (512, 512), 4),
+                                      # four (FP32) / two (FP64) points per thread,
+                                      # with bands and with planes too large for them
+                                      (3, (128, 64, 64), 2), (3, (256, 256, 8), 4)])
 def test_fd_shapes_parity(ndim, n, p, prec):
     dx = (1.0, 0.8, 1.2)[:ndim]
     cfg = I.make_config(ndim, n, dx, p, I.PAPER_FE)

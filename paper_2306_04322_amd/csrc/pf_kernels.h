@@ -47,6 +47,9 @@
 #ifndef PF_ROW_ROWS_LONG
 #define PF_ROW_ROWS_LONG 4  // rows per row-pass work-group, float, Nx = 1024
 #endif
+#ifndef PF_ROW_MULT_SHORT
+#define PF_ROW_MULT_SHORT 1  // row-pass work-group multiple, float, Nx < 1024 (2 and 4 measured slower)
+#endif
 #ifndef PF_ROW_NW
 #define PF_ROW_NW 4  // wavefronts per row-pass work-group (0: p_max + 1)
 #endif
@@ -332,18 +335,23 @@ struct RGeom {
   static constexpr int SLOTS = PMAX + 2;
   static constexpr int SLOT_C = lds_span(NH);  // complex values per slot (padded layout)
   static constexpr long ROW_BYTES = long(SLOTS) * SLOT_C * 2 * long(sizeof(T));
-  // float rows of 1024 points: PF_ROW_ROWS_LONG rows per work-group with
-  // PF_ROW_NW wavefronts each, so the F transforms of a row that do not
-  // divide over its own wavefronts (F = 5 over 4) spread evenly over the
-  // CU's four SIMDs instead of all landing on the first wavefront's SIMD
-  static constexpr bool LONG_MULTI = !SM && NX == 1024 && sizeof(T) == 4 && PF_ROW_ROWS_LONG > 1 &&
-                                     PF_ROW_ROWS_LONG * ROW_BYTES <= 160 * 1024;
-  static constexpr int ROWS = SM ? 1 : NX < 1024 ? 1024 / NX : (LONG_MULTI ? PF_ROW_ROWS_LONG : 1);
+  // Float rows: MULT times the rows and the wavefronts of the base form
+  // (1024/Nx rows or one row, PF_ROW_NW wavefronts), so the F transforms of
+  // a row that do not divide over the wavefronts (F = 5 over 4) spread
+  // evenly over the CU's four SIMDs instead of all landing on the first
+  // wavefront's SIMD.
+  static constexpr int BASE_ROWS = SM ? 1 : (NX >= 1024 ? 1 : 1024 / NX);
+  static constexpr int MULT_WANT = NX == 1024 ? PF_ROW_ROWS_LONG : PF_ROW_MULT_SHORT;
+  static constexpr bool MULTI = !SM && NX <= 1024 && sizeof(T) == 4 && PF_ROW_NW > 0 && MULT_WANT > 1 &&
+                                PF_ROW_NW * MULT_WANT <= 16 &&
+                                MULT_WANT * BASE_ROWS * ROW_BYTES <= 160 * 1024;
+  static constexpr int MULT = MULTI ? MULT_WANT : 1;
+  static constexpr int ROWS = BASE_ROWS * MULT;
   static constexpr int NW = SM ? (PMAX + UPW) / UPW  // ceil((PMAX + 1) / UPW)
-                               : (PF_ROW_NW > 0 ? PF_ROW_NW * (LONG_MULTI ? ROWS : 1) : PMAX + 1);
+                               : (PF_ROW_NW > 0 ? PF_ROW_NW * MULT : PMAX + 1);
   static constexpr int WG = 64 * NW;
   static constexpr long LDS_BYTES = long(ROWS) * ROW_BYTES;
-  static constexpr bool FITS = WAVE_OK && LDS_BYTES <= (LONG_MULTI ? 160 : 96) * 1024;
+  static constexpr bool FITS = WAVE_OK && LDS_BYTES <= (MULTI ? 160 : 96) * 1024;
   // register budget: enough waves per SIMD for four work-groups per CU
   static constexpr int MIN_WAVES = (sizeof(T) == 4 && PMAX <= 4) ? PF_ROW_MIN_WAVES : 1;
 };

@@ -154,6 +154,35 @@ def test_full_size_3d_256_z_invariant(prec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("n", [(128, 64, 64), (512, 64, 16), (1024, 16, 32)])
+def test_z_invariant_3d_matches_2d(n, prec):
+    """Grids with enough rows for the row pass's multi-row work-groups at
+    Nx = 128, 512 and 1024: a z-invariant state evolves like the 2D problem
+    on one plane, which the oracle computes; every plane is compared."""
+    nx, ny, nz = n
+    cfg3 = I.make_config(3, n, 1.0, 4, I.PAPER_FE)
+    cfg2 = I.make_config(2, (nx, ny), 1.0, 4, I.PAPER_FE)
+    u2 = I.random_ic(cfg2, seed=7, c0=0.45)
+    if prec == "f32":
+        u2 = fp32_rounded(u2)
+    u3 = np.ascontiguousarray(np.broadcast_to(u2[:, None, :, :], (5, nz, ny, nx)))
+    announce("fs z-invariant", n, prec)
+    gpu_or_fail()
+    from paper_2306_04322_amd.pfspec import Solver
+    s = Solver(cfg3, prec)
+    s.set_fields(u3)
+    # dt = 0.01: the order parameters keep most of their size over the three
+    # steps (at dt = 0.1 they fall to 1e-10, where a relative error says
+    # nothing about the arithmetic)
+    s.step_fs(0.01, 3)
+    got = s.get_fields()
+    ref = ofs.fs_run(u2, cfg2, 0.01, 3)
+    for z in range(nz):
+        errs = rel_l2(got[:, z], ref)
+        assert max_rel(errs) <= (1e-11 if prec == "f64" else 1e-5), (z, errs)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_full_size_3d_256_single_mode_closed_form(prec):
     """3D 256^3, c + 4 eta (the 3D benchmark shape): with eta = 0 exactly the
     c equation is linear under the paper's f_chem (df/dc = 2 rho2 (c - c_alpha)),

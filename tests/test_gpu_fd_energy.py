@@ -49,7 +49,9 @@ def test_fd_workload_parity(prec):
                                       (2, (512, 512), 4),
                                       # four (FP32) / two (FP64) points per thread,
                                       # with bands and with planes too large for them
-                                      (3, (128, 64, 64), 2), (3, (256, 256, 8), 4)])
+                                      (3, (128, 64, 64), 2), (3, (256, 256, 8), 4),
+                                      # longest axes
+                                      (2, (4096, 8), 1), (2, (8, 4096), 2), (3, (8, 8, 1024), 2)])
 def test_fd_shapes_parity(ndim, n, p, prec):
     dx = (1.0, 0.8, 1.2)[:ndim]
     cfg = I.make_config(ndim, n, dx, p, I.PAPER_FE)

@@ -49,6 +49,8 @@ SHAPES = [
     (2, (8, 8), 1), (2, (16, 32), 2), (2, (128, 64), 4), (2, (32, 256), 3),
     (2, (512, 16), 2), (2, (64, 64), 8), (2, (4096, 8), 1), (2, (8, 2048), 2),
     (3, (8, 8, 8), 2), (3, (16, 8, 32), 4), (3, (32, 32, 16), 1), (3, (8, 64, 8), 5),
+    # longest strided axes: 4096 in 2D, 1024 along y and along z in 3D
+    (2, (8, 4096), 2), (3, (16, 1024, 8), 2), (3, (8, 8, 1024), 1),
 ]
 
 

@@ -219,8 +219,9 @@ def main(argv=None):
                                   "f_chem, seeded uniform IC c=0.5+0.05U(-1,1), eta=0.1U(0,1), dt=0.1",
                       "grid": [1024, 1024], "fields": 5, "dt": dt, "precision": "f32"},
            "roofline": roof,
-           # whole step against the survey's unfused Algorithm 1 figure of
-           # 9 F s bytes per grid point (F = 5, s = 4)
+           # whole step against the unfused Algorithm 1 figure, in which each
+           # stage reads and writes HBM once: 9 F s bytes per grid point
+           # (F = 5, s = 4)
            "step_roofline_9Fs": {"bytes_per_point": 9 * 5 * 4,
                                  "achieved_GBs": round(value * 9 * 5 * 4 / 1e9, 1),
                                  "frac": round(value * 9 * 5 * 4 / (HBM_PEAK_GBS * 1e9), 4)}}

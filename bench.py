@@ -162,7 +162,7 @@ def main(argv=None):
                     help="also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the FS step is benchmarked on a single "
+        print("bench.py: runs on one GPU only (the FS step is benchmarked on a single "
               "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         return 2
 

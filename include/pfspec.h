@@ -40,7 +40,7 @@ extern "C" {
 typedef enum {
   PF_OK = 0,
   PF_ERR_INVALID = 1,     /* bad argument or configuration */
-  PF_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
+  PF_ERR_UNSUPPORTED = 2, /* valid request the library does not implement */
   PF_ERR_NOMEM = 3,       /* caller-supplied buffer too small */
   PF_ERR_HIP = 4,         /* a HIP runtime call failed */
   PF_ERR_NONFINITE = 5    /* a reduction produced NaN or Inf */

@@ -138,7 +138,7 @@ def cpu_baseline(cfg, u0, dt, budget_s=20.0):
 def traffic_from_profile(kind):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if the
     kernel source is unchanged since they were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_w2_f32.json")
+    path = os.path.join(ROOT, "profiles", "fs2d_1024_f32_row_col_traffic.json")
     if not os.path.exists(path):
         return None
     try:

@@ -336,10 +336,9 @@ struct RGeom {
   static constexpr int SLOT_C = lds_span(NH);  // complex values per slot (padded layout)
   static constexpr long ROW_BYTES = long(SLOTS) * SLOT_C * 2 * long(sizeof(T));
   // Float rows: MULT times the rows and the wavefronts of the base form
-  // (1024/Nx rows or one row, PF_ROW_NW wavefronts), so the F transforms of
-  // a row that do not divide over the wavefronts (F = 5 over 4) spread
-  // evenly over the CU's four SIMDs instead of all landing on the first
-  // wavefront's SIMD.
+  // (1024/Nx rows or one row, PF_ROW_NW wavefronts).  Meant to spread the
+  // transforms of rows whose F does not divide over the wavefronts (F = 5
+  // over 4) evenly over the CU's SIMDs; measured faster at Nx = 1024 only.
   static constexpr int BASE_ROWS = SM ? 1 : (NX >= 1024 ? 1 : 1024 / NX);
   static constexpr int MULT_WANT = NX == 1024 ? PF_ROW_ROWS_LONG : PF_ROW_MULT_SHORT;
   static constexpr bool MULTI = !SM && NX <= 1024 && sizeof(T) == 4 && PF_ROW_NW > 0 && MULT_WANT > 1 &&

@@ -47,6 +47,9 @@
 #ifndef PF_ROW_ROWS_LONG
 #define PF_ROW_ROWS_LONG 4  // rows per row-pass work-group, float, Nx = 1024
 #endif
+#ifndef PF_ROW_MULT_2048
+#define PF_ROW_MULT_2048 2  // row-pass work-group multiple, float, Nx = 2048
+#endif
 #ifndef PF_ROW_MULT_SHORT
 #define PF_ROW_MULT_SHORT 1  // row-pass work-group multiple, float, Nx < 1024 (2 and 4 measured slower)
 #endif
@@ -338,10 +341,11 @@ struct RGeom {
   // Float rows: MULT times the rows and the wavefronts of the base form
   // (1024/Nx rows or one row, PF_ROW_NW wavefronts).  Meant to spread the
   // transforms of rows whose F does not divide over the wavefronts (F = 5
-  // over 4) evenly over the CU's SIMDs; measured faster at Nx = 1024 only.
+  // over 4) evenly over the CU's SIMDs; measured faster at Nx = 1024 (four
+  // rows) and 2048 (two rows) only.
   static constexpr int BASE_ROWS = SM ? 1 : (NX >= 1024 ? 1 : 1024 / NX);
-  static constexpr int MULT_WANT = NX == 1024 ? PF_ROW_ROWS_LONG : PF_ROW_MULT_SHORT;
-  static constexpr bool MULTI = !SM && NX <= 1024 && sizeof(T) == 4 && PF_ROW_NW > 0 && MULT_WANT > 1 &&
+  static constexpr int MULT_WANT = NX == 2048 ? PF_ROW_MULT_2048 : NX == 1024 ? PF_ROW_ROWS_LONG : PF_ROW_MULT_SHORT;
+  static constexpr bool MULTI = !SM && NX <= 2048 && sizeof(T) == 4 && PF_ROW_NW > 0 && MULT_WANT > 1 &&
                                 PF_ROW_NW * MULT_WANT <= 16 &&
                                 MULT_WANT * BASE_ROWS * ROW_BYTES <= 160 * 1024;
   static constexpr int MULT = MULTI ? MULT_WANT : 1;

@@ -51,6 +51,8 @@ SHAPES = [
     (3, (8, 8, 8), 2), (3, (16, 8, 32), 4), (3, (32, 32, 16), 1), (3, (8, 64, 8), 5),
     # longest strided axes: 4096 in 2D, 1024 along y and along z in 3D
     (2, (8, 4096), 2), (3, (16, 1024, 8), 2), (3, (8, 8, 1024), 1),
+    # 2048-point rows
+    (2, (2048, 64), 4),
 ]
 
 

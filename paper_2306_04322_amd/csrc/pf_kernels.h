@@ -62,6 +62,9 @@
 #ifndef PF_FAST_RCP
 #define PF_FAST_RCP 1  // float k-space multipliers through the hardware reciprocal
 #endif
+#ifndef PF_COL_WG_MAX_LONG
+#define PF_COL_WG_MAX_LONG 1024  // largest column work-group, float, length 4096 (2-column tiles)
+#endif
 #ifndef PF_COL_E_LONG_F32
 #define PF_COL_E_LONG_F32 8  // elements per lane, float column transforms of length >= 512
 #endif
@@ -867,7 +870,8 @@ struct ColGeom {
   static constexpr int CB = N >= 512 ? (sizeof(T) == 8 ? PF_COL_CB_LONG_F64 : PF_COL_CB_LONG_F32)
                                     : (sizeof(T) == 8 ? 8 : 16);
   static constexpr int C0 = (CB * TEAM < 64) ? 64 / TEAM : CB;
-  static constexpr int C = (C0 * TEAM > 512) ? (512 / TEAM > 0 ? 512 / TEAM : 1) : C0;
+  static constexpr int WGMAX = (sizeof(T) == 4 && N >= 4096) ? PF_COL_WG_MAX_LONG : 512;
+  static constexpr int C = (C0 * TEAM > WGMAX) ? (WGMAX / TEAM > 0 ? WGMAX / TEAM : 1) : C0;
   static constexpr int WG = C * TEAM;
   static constexpr int MIN_WAVES = sizeof(T) == 4 ? PF_COL_MIN_WAVES : 1;
 };

@@ -10,8 +10,10 @@
 // field costs 5 (2D) or 7 (3D) loads per V points instead of per point.
 // The y and z neighbours are rows that neighbouring work-groups also read;
 // on grids whose neighbour rows or planes fit in L2, each XCD takes a
-// contiguous band of the grid so those re-reads stay in its own L2.  The
-// energy kernel keeps one thread per point.
+// contiguous band of the grid so those re-reads stay in its own L2.  On
+// larger 3D grids each thread instead marches along z over a few planes and
+// keeps the neighbour planes in registers.  The energy kernel keeps one
+// thread per point.
 // Periodic wrap uses power-of-two masks instead of ghost layers.
 #include "pf_kernels.h"
 #include "pf_launch.h"
@@ -186,6 +188,132 @@ __global__ void __launch_bounds__(256) fd_c_kernel(FdArgs<T> a, int bands) {
   st_vec<T, V>(a.out + i0, o);
 }
 
+// 3D grids whose neighbour planes do not fit in L2: each thread takes V
+// consecutive x points of one (y, x) column and marches over ZB consecutive
+// planes, keeping the planes z - 1, z and z + 1 of every field it reads in
+// registers, so each plane comes from HBM once per block of ZB planes
+// instead of three times.  Same arithmetic, in the same order, as the
+// one-plane kernels.
+template <typename T, int V>
+__device__ __forceinline__ void lap_vec_z(const T* __restrict__ v, const FdVec<T, V>& zm,
+                                          const FdVec<T, V>& cv, const FdVec<T, V>& zp,
+                                          long long row, int x0, long long ym, long long yp,
+                                          const FdArgs<T>& a, T* out) {
+  const FdVec<T, V> vm = ld_vec<T, V>(v + ym), vp = ld_vec<T, V>(v + yp);
+  const T xl = v[row + ((x0 - 1) & (a.nx - 1))], xr = v[row + ((x0 + V) & (a.nx - 1))];
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    const T c = cv.v[k];
+    const T left = k == 0 ? xl : cv.v[k - 1];
+    const T right = k == V - 1 ? xr : cv.v[k + 1];
+    T r = (right - T(2) * c + left) * a.ix2 + (vp.v[k] - T(2) * c + vm.v[k]) * a.iy2;
+    r += (zp.v[k] - T(2) * c + zm.v[k]) * a.iz2;
+    out[k] = r;
+  }
+}
+
+struct ZCol {
+  long long plane, rest, ymr, ypr;  // plane size; (y, x0) offset in a plane; y -/+ 1 rows
+  int x0, z0;
+};
+
+template <typename T, int V>
+__device__ __forceinline__ bool zcol(const FdArgs<T>& a, int zb, ZCol& q) {
+  const long long nxv = a.nx / V;
+  const long long per = nxv * a.ny;  // vectors per plane
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= per * (a.nz / zb)) return false;
+  const long long vin = t % per;
+  q.z0 = int(t / per) * zb;
+  q.x0 = int(vin % nxv) * V;
+  const int y = int(vin / nxv);
+  q.plane = (long long)a.nx * a.ny;
+  q.rest = (long long)y * a.nx + q.x0;
+  q.ymr = (long long)((y - 1) & (a.ny - 1)) * a.nx + q.x0;
+  q.ypr = (long long)((y + 1) & (a.ny - 1)) * a.nx + q.x0;
+  return true;
+}
+
+template <typename T, int PMAX, int V>
+__global__ void __launch_bounds__(256) fd_mu_z_kernel(FdArgs<T> a, int zb) {
+  ZCol q;
+  if (!zcol<T, V>(a, zb, q)) return;
+  const int p = a.F - 1;
+  FdVec<T, V> m[PMAX + 1], c[PMAX + 1], n[PMAX + 1];
+  const long long zm0 = (long long)((q.z0 - 1) & (a.nz - 1)) * q.plane + q.rest;
+  const long long zc0 = (long long)q.z0 * q.plane + q.rest;
+#pragma unroll
+  for (int f = 0; f <= PMAX; ++f)
+    if (f <= p) {
+      m[f] = ld_vec<T, V>(a.in + f * a.P + zm0);
+      c[f] = ld_vec<T, V>(a.in + f * a.P + zc0);
+    }
+  for (int k = 0; k < zb; ++k) {
+    const int z = q.z0 + k;
+    const long long zoff = (long long)z * q.plane;
+    const long long i0 = zoff + q.rest;
+    const long long zn = (long long)((z + 1) & (a.nz - 1)) * q.plane + q.rest;
+#pragma unroll
+    for (int f = 0; f <= PMAX; ++f)
+      if (f <= p) n[f] = ld_vec<T, V>(a.in + f * a.P + zn);
+    T gc[V], ge[PMAX][V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      T eta[PMAX], g[PMAX];
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j) {
+        eta[j] = (j < p) ? c[j + 1].v[e] : T(0);
+        g[j] = T(0);
+      }
+      fe_grad<T, PMAX>(a.fe, p, c[0].v[e], eta, gc[e], g);
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j) ge[j][e] = g[j];
+    }
+    const long long row = zoff + (q.rest - q.x0);
+    T l[V], o[V];
+    lap_vec_z<T, V>(a.in, m[0], c[0], n[0], row, q.x0, zoff + q.ymr, zoff + q.ypr, a, l);
+#pragma unroll
+    for (int e = 0; e < V; ++e) o[e] = gc[e] - a.kc * l[e];
+    st_vec<T, V>(a.mu + i0, o);
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j)
+      if (j < p) {
+        const T* ev = a.in + (j + 1) * a.P;
+        lap_vec_z<T, V>(ev, m[j + 1], c[j + 1], n[j + 1], row, q.x0, zoff + q.ymr, zoff + q.ypr, a, l);
+#pragma unroll
+        for (int e = 0; e < V; ++e) o[e] = c[j + 1].v[e] - a.dtL * (ge[j][e] - a.ke * l[e]);
+        st_vec<T, V>(a.out + (j + 1) * a.P + i0, o);
+      }
+#pragma unroll
+    for (int f = 0; f <= PMAX; ++f) {
+      m[f] = c[f];
+      c[f] = n[f];
+    }
+  }
+}
+
+template <typename T, int V>
+__global__ void __launch_bounds__(256) fd_c_z_kernel(FdArgs<T> a, int zb) {
+  ZCol q;
+  if (!zcol<T, V>(a, zb, q)) return;
+  FdVec<T, V> m = ld_vec<T, V>(a.mu + (long long)((q.z0 - 1) & (a.nz - 1)) * q.plane + q.rest);
+  FdVec<T, V> c = ld_vec<T, V>(a.mu + (long long)q.z0 * q.plane + q.rest);
+  for (int k = 0; k < zb; ++k) {
+    const int z = q.z0 + k;
+    const long long zoff = (long long)z * q.plane;
+    const long long i0 = zoff + q.rest;
+    const FdVec<T, V> n = ld_vec<T, V>(a.mu + (long long)((z + 1) & (a.nz - 1)) * q.plane + q.rest);
+    const FdVec<T, V> cu = ld_vec<T, V>(a.in + i0);
+    T l[V], o[V];
+    lap_vec_z<T, V>(a.mu, m, c, n, zoff + (q.rest - q.x0), q.x0, zoff + q.ymr, zoff + q.ypr, a, l);
+#pragma unroll
+    for (int e = 0; e < V; ++e) o[e] = cu.v[e] + a.dtM * l[e];
+    st_vec<T, V>(a.out + i0, o);
+    m = c;
+    c = n;
+  }
+}
+
 // partials[block] = {sum f(u), sum_d (dc/dx_d)^2, sum_i sum_d (deta_i/dx_d)^2, sum c}
 // with forward differences, accumulated in double.
 template <typename T, int PMAX>
@@ -232,6 +360,13 @@ static int fd_vec_width(long long P) {
   return 1;
 }
 
+#ifndef PF_FD_ZMARCH
+#define PF_FD_ZMARCH 1  // 3D grids without bands: threads march along z
+#endif
+#ifndef PF_FD_ZB
+#define PF_FD_ZB 8  // planes per marching thread
+#endif
+
 // XCD bands pay while the three neighbour rows (2D) or planes (3D) of all F
 // fields fit in half of one XCD's 4 MiB L2; beyond that (3D 256^3) the plain
 // round-robin order, which sweeps the whole GPU through the grid together
@@ -246,6 +381,13 @@ template <typename T, int PMAX, int V>
 static int fd_go_v(int which, const FdArgs<T>& a, hipStream_t s) {
   const long long nv = a.P / V;  // nx >= 8 is a multiple of V
   const int bands = fd_bands(a);
+  if (PF_FD_ZMARCH && a.ndim == 3 && !bands) {
+    const int zb = a.nz < PF_FD_ZB ? a.nz : PF_FD_ZB;  // both powers of two
+    const int grid = int((nv / zb + 255) / 256);
+    if (which == 0) hipLaunchKernelGGL((fd_mu_z_kernel<T, PMAX, V>), dim3(grid), dim3(256), 0, s, a, zb);
+    else hipLaunchKernelGGL((fd_c_z_kernel<T, V>), dim3(grid), dim3(256), 0, s, a, zb);
+    return grid;
+  }
   int grid = int((nv + 255) / 256);
   if (bands) grid = (grid + 7) / 8 * 8;
   if (which == 0) hipLaunchKernelGGL((fd_mu_kernel<T, PMAX, V>), dim3(grid), dim3(256), 0, s, a, bands);

@@ -50,6 +50,8 @@ def test_fd_workload_parity(prec):
                                       # four (FP32) / two (FP64) points per thread,
                                       # with bands and with planes too large for them
                                       (3, (128, 64, 64), 2), (3, (256, 256, 8), 4),
+                                      # planes too large for bands, two blocks of 16 planes
+                                      (3, (256, 256, 32), 4),
                                       # longest axes
                                       (2, (4096, 8), 1), (2, (8, 4096), 2), (3, (8, 8, 1024), 2)])
 def test_fd_shapes_parity(ndim, n, p, prec):

@@ -12,7 +12,7 @@
 // on grids whose neighbour rows or planes fit in L2, each XCD takes a
 // contiguous band of the grid so those re-reads stay in its own L2.  On
 // larger 3D grids each thread instead marches along z over a few planes and
-// keeps the neighbour planes in registers.  The energy kernel keeps one
+// keeps its neighbour planes in registers.  The energy kernel keeps one
 // thread per point.
 // Periodic wrap uses power-of-two masks instead of ghost layers.
 #include "pf_kernels.h"
@@ -191,9 +191,9 @@ __global__ void __launch_bounds__(256) fd_c_kernel(FdArgs<T> a, int bands) {
 // 3D grids whose neighbour planes do not fit in L2: each thread takes V
 // consecutive x points of one (y, x) column and marches over ZB consecutive
 // planes, keeping the planes z - 1, z and z + 1 of every field it reads in
-// registers, so each plane comes from HBM once per block of ZB planes
-// instead of three times.  Same arithmetic, in the same order, as the
-// one-plane kernels.
+// registers, so a thread loads each of its planes once per block of ZB
+// planes instead of three times.  Same arithmetic, in the same order, as
+// the one-plane kernels.
 template <typename T, int V>
 __device__ __forceinline__ void lap_vec_z(const T* __restrict__ v, const FdVec<T, V>& zm,
                                           const FdVec<T, V>& cv, const FdVec<T, V>& zp,

@@ -10,6 +10,11 @@ import numpy as np
 # drive eta towards zero, where a relative error is meaningless.
 NORM_FLOOR = 1e-30
 
+# Kinetic coefficients that differ pairwise (M != L, kappa_c != kappa_eta):
+# a kernel that used one coefficient in place of another fails a parity case
+# run with them (the paper's own values have M = L and kappa_c = kappa_eta).
+DISTINCT = {"M": 5.0, "kappa_c": 3.0, "L": 4.0, "kappa_eta": 2.0}
+
 
 def rel_l2(got, ref):
     """Per-field ||got - ref||_2 / ||ref||_2 (None below the floor)."""

@@ -8,7 +8,7 @@ from oracle import energy as oen
 from oracle import fd as ofd
 from oracle import fs as ofs
 from paper_2306_04322_amd import inputs as I
-from parity_util import announce, fp32_rounded, gpu_or_fail, max_rel, rel_l2
+from parity_util import DISTINCT, announce, fp32_rounded, gpu_or_fail, max_rel, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -50,13 +50,17 @@ def test_fd_workload_parity(prec):
                                       # four (FP32) / two (FP64) points per thread,
                                       # with bands and with planes too large for them
                                       (3, (128, 64, 64), 2), (3, (256, 256, 8), 4),
-                                      # planes too large for bands, two blocks of 16 planes
-                                      (3, (256, 256, 32), 4),
+                                      # planes too large for bands: threads march along z,
+                                      # four blocks of 8 planes (p = 4), two blocks with
+                                      # p = 2, and one block with p = 8 at one point per
+                                      # thread (FP64; in FP32 these planes take XCD bands)
+                                      (3, (256, 256, 32), 4), (3, (256, 256, 16), 2),
+                                      (3, (128, 128, 8), 8),
                                       # longest axes
                                       (2, (4096, 8), 1), (2, (8, 4096), 2), (3, (8, 8, 1024), 2)])
 def test_fd_shapes_parity(ndim, n, p, prec):
     dx = (1.0, 0.8, 1.2)[:ndim]
-    cfg = I.make_config(ndim, n, dx, p, I.PAPER_FE)
+    cfg = I.make_config(ndim, n, dx, p, I.PAPER_FE, **DISTINCT)
     u0 = I.random_ic(cfg, seed=9)
     if prec == "f32":
         u0 = fp32_rounded(u0)
@@ -76,17 +80,17 @@ def test_energy_parity(case, scheme, prec):
         cfg, w = I.workload_config("WO")
         u0 = I.workload_ic(cfg, w)
     elif case == "rand2d":
-        cfg = I.make_config(2, (64, 128), (0.5, 1.5), 2, I.PAPER_FE, "fd4")
+        cfg = I.make_config(2, (64, 128), (0.5, 1.5), 2, I.PAPER_FE, "fd4", **DISTINCT)
         u0 = I.random_ic(cfg, 4)
     elif case == "rand3d":
-        cfg = I.make_config(3, (16, 32, 8), 1.0, 4, I.PAPER_FE)
+        cfg = I.make_config(3, (16, 32, 8), 1.0, 4, I.PAPER_FE, **DISTINCT)
         u0 = I.random_ic(cfg, 5, c0=0.45)
     elif case == "rand3d_wide":
         # several full column tiles plus the Nyquist column on both strided axes
-        cfg = I.make_config(3, (64, 32, 32), (1.0, 0.9, 1.1), 2, I.PAPER_FE)
+        cfg = I.make_config(3, (64, 32, 32), (1.0, 0.9, 1.1), 2, I.PAPER_FE, **DISTINCT)
         u0 = I.random_ic(cfg, 8, c0=0.45)
     else:
-        cfg = I.make_config(2, 32, 1.0, 3, I.POLY_FE)
+        cfg = I.make_config(2, 32, 1.0, 3, I.POLY_FE, **DISTINCT)
         u0 = I.random_ic(cfg, 6)
     if prec == "f32":
         u0 = fp32_rounded(u0)

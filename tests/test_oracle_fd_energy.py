@@ -9,10 +9,16 @@ from paper_2306_04322_amd import inputs as I
 GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
 
 
+# Kinetic coefficients that differ pairwise (M != L, kappa_c != kappa_eta), so
+# that a pin fails if any coefficient is used in place of another.
+DISTINCT = {"M": 5.0, "kappa_c": 3.0, "L": 4.0, "kappa_eta": 2.0}
+
+
 def test_fd_linear_mode_closed_form():
     # eta = 0: the FD step on c is linear; mode factor 1 - dt M q (f_cc + kappa_c q)
-    # with q the 5-point symbol of Eq. (17)
-    cfg = I.make_config(2, (16, 32), 1.0, 2, I.PAPER_FE)
+    # with q the 5-point symbol of Eq. (17) and f_cc = 2 rho2 = 4 (Sec. 2.2 FD
+    # kernels (i) and (ii); Eq. (2))
+    cfg = I.make_config(2, (16, 32), 1.0, 2, I.PAPER_FE, **DISTINCT)
     m = (3, 2)
     u0 = I.single_mode(cfg, [0.5, 0.0, 0.0], 1e-3, 0, m)
     q = sum(kspace.sq_axis(cfg["n"][d], 1.0, "fd2")[m[d]] for d in range(2))
@@ -21,6 +27,48 @@ def test_fd_linear_mode_closed_form():
     got = fd.fd_run(u0, cfg, dt, 20)
     assert np.max(np.abs(got[0] - 0.5 - G ** 20 * (u0[0] - 0.5))) <= 1e-15
     assert np.max(np.abs(got[1:])) == 0.0
+
+
+@pytest.mark.parametrize("ndim,n,dx,m", [(2, (16, 32), (1.0, 0.8), (3, 2)),
+                                         (3, (8, 16, 8), (1.0, 1.2, 0.9), (1, 2, 3))])
+def test_fd_eta_mode_decay_closed_form(ndim, n, dx, m):
+    # A small eta_2 mode eps cos(k.x) about the uniform state (c0, eta = 0):
+    # Eq. (3) with the FD Laplacian (Sec. 2.2 FD kernel (iii)) is, to first
+    # order in eps, eta' = eta - dt L (f_etaeta eta - kappa_eta lap_h eta), and
+    # lap_h maps the mode to -q times itself (q the symbol of Eq. (17)/(20)).
+    # f_etaeta = 2 w at eta = 0 for any c, so the amplitude ratio per step is
+    # G = 1 - dt L (2 w + kappa_eta q), up to O(eps) from the cubic terms.
+    cfg = I.make_config(ndim, n, dx, 3, I.PAPER_FE, **DISTINCT)
+    eps = 1e-7
+    u0 = I.single_mode(cfg, [0.45, 0.0, 0.0, 0.0], eps, 2, m)
+    q = sum(kspace.sq_axis(cfg["n"][d], cfg["dx"][d], "fd2")[m[d]] for d in range(ndim))
+    dt = 2e-3
+    G = 1.0 - dt * 4.0 * (2.0 * 1.0 + 2.0 * q)
+    mode = u0[2] / eps
+    u = u0
+    for k in range(1, 6):
+        u = fd.fd_step(u, cfg, dt)
+        amp = float(np.sum(u[2] * mode) / np.sum(mode * mode))
+        assert abs(amp / (eps * G ** k) - 1.0) <= 1e-5, (k, amp, eps * G ** k)
+    # the other order parameters stay zero, and c stays uniform to O(eps^3)
+    assert np.max(np.abs(u[1])) == 0.0 and np.max(np.abs(u[3])) == 0.0
+    assert np.max(np.abs(u[0] - 0.45)) <= 1e-15
+
+
+def test_fd_mu_uses_kappa_c_and_c_update_uses_M():
+    # One FD step from a single c mode with eta = 0 on a grid where the
+    # exact factor 1 - dt M q (f_cc + kappa_c q) differs under any swap of
+    # (M, L) or (kappa_c, kappa_eta); checked in the first step, where it is
+    # exact (the step is linear in c at eta = 0 for f_chem).
+    cfg = I.make_config(2, (8, 8), 1.0, 1, I.PAPER_FE, **DISTINCT)
+    u0 = I.single_mode(cfg, [0.35, 0.0], 1e-2, 0, (1, 1))
+    q = 2 * kspace.sq_axis(8, 1.0, "fd2")[1]
+    dt = 1e-3
+    got = fd.fd_step(u0, cfg, dt)
+    for M, kc in ((5.0, 3.0), (4.0, 3.0), (5.0, 2.0), (4.0, 2.0)):
+        G = 1 - dt * M * q * (4.0 + kc * q)
+        ok = np.max(np.abs(got[0] - 0.35 - G * (u0[0] - 0.35))) <= 1e-16
+        assert ok == (M == 5.0 and kc == 3.0), (M, kc)
 
 
 def test_fd_uses_fields_at_time_t():
@@ -64,6 +112,40 @@ def test_spectral_gradient_energy_single_mode():
     assert abs(E[1] - dV * np.sum(2.0 * (u[0] - 0.3) ** 2)) <= 1e-13
     assert abs(E[4] - dV * 0.3 * 128) <= 1e-12
     assert abs(E[0] - E[1] - E[2] - E[3]) <= 1e-13
+
+
+@pytest.mark.parametrize("ndim,n,dx,mc,me", [(2, (16, 8), (0.5, 1.0), (2, 0), (3, 1)),
+                                               (3, (8, 8, 16), (1.0, 0.7, 1.3), (1, 0, 2), (2, 3, 1))])
+def test_gradient_energies_of_single_modes(ndim, n, dx, mc, me):
+    # Eq. (1) gradient parts for c = c0 + B cos(k_c.x), eta_1 = A cos(k_e.x),
+    # eta_2 = 0, with kappa_c != kappa_eta.  Over a full period the mean of
+    # sin^2 is 1/2 (k not 0 or Nyquist on every axis), so
+    #   spectral: sum |grad v|^2 = amp^2 |xi|^2 P / 2       (|xi|^2 of Eq. (16)/(19))
+    #   FD form:  sum of forward-difference squares = amp^2 q P / 2,
+    #             q = sum_d 2 (1 - cos(xi_d dx_d)) / dx_d^2 (Eq. (17)/(20)),
+    # each term weighted by kappa / 2 and dV.
+    cfg = I.make_config(ndim, n, dx, 2, I.PAPER_FE, **DISTINCT)
+    A, B = 0.03, 0.02
+    u = I.single_mode(cfg, [0.5, 0.0, 0.0], B, 0, mc)
+    u[1] = I.single_mode(cfg, [0.0, 0.0, 0.0], A, 1, me)[1]
+    P = int(np.prod(n))
+    dV = float(np.prod(dx))
+
+    def sym(m, kmode):
+        return sum(kspace.sq_axis(n[d], dx[d], kmode)[m[d]] for d in range(ndim))
+
+    Efs = energy.energy(u, cfg, "fs")
+    Efd = energy.energy(u, cfg, "fd")
+    exp_fs_c = 0.5 * 3.0 * dV * B * B * sym(mc, "spectral") * P / 2
+    exp_fs_e = 0.5 * 2.0 * dV * A * A * sym(me, "spectral") * P / 2
+    exp_fd_c = 0.5 * 3.0 * dV * B * B * sym(mc, "fd2") * P / 2
+    exp_fd_e = 0.5 * 2.0 * dV * A * A * sym(me, "fd2") * P / 2
+    assert abs(Efs[2] - exp_fs_c) <= 1e-13 * exp_fs_c
+    assert abs(Efs[3] - exp_fs_e) <= 1e-13 * exp_fs_e
+    assert abs(Efd[2] - exp_fd_c) <= 1e-13 * exp_fd_c
+    assert abs(Efd[3] - exp_fd_e) <= 1e-13 * exp_fd_e
+    for E in (Efs, Efd):
+        assert abs(E[0] - E[1] - E[2] - E[3]) <= 1e-13 * abs(E[0])
 
 
 def test_fd_gradient_energy_is_summation_by_parts():

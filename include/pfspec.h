@@ -81,10 +81,16 @@ typedef struct {
 
 typedef struct pf_handle pf_handle;
 
-/* Validate `cfg` and build the host-side plan (twiddle and per-axis
- * frequency tables, computed in double precision).  Makes no HIP call, so a
- * bad configuration is reported without touching the GPU.
- * Returns PF_ERR_INVALID for a malformed config and *out = NULL. */
+/* Validate `cfg` and build the host-side plan: the variables Algorithm 1
+ * initialises before its time loop (the grid x_j = j dx on a periodic box of
+ * N dx per axis, the frequency index vectors and |xi|^2 of Eq. (16)/(19), or
+ * the FS-FD symbols of Eq. (17)/(18)/(20)/(21)), the DFT twiddles, and the
+ * constants of Sec. 2.1 (the free-energy coefficients of f_chem and the
+ * kinetic coefficients M, kappa_c, L, kappa_eta of Eq. (2), (3)).  The
+ * tables are computed in double precision on the host.  Makes no HIP call,
+ * so a bad configuration is reported without touching the GPU.
+ * Returns PF_ERR_INVALID for a malformed config and *out = NULL; on success
+ * the caller owns *out and releases it with pf_destroy. */
 pf_status pf_create(const pf_config* cfg, pf_handle** out);
 
 /* Release host plan state.  Does not touch caller buffers.  NULL is ignored. */

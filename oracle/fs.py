@@ -50,11 +50,13 @@ def _real(z, what):
     return z.real.copy()
 
 
-def fs_run(u0, cfg, dt, nsteps, record_every=0):
+def fs_run(u0, cfg, dt, nsteps, record_every=0, workers=1):
     """Advance `u0` (F, ...) by `nsteps` FS steps of size `dt`.
 
     Returns the final fields, or (final, [snapshots]) when `record_every`
-    is positive (snapshot list starts with u0).
+    is positive (snapshot list starts with u0).  `workers` > 1 runs the
+    transforms of the F fields on that many threads (bit-identical result;
+    for the large grids of the tests).
     """
     shape, dxs, axes = geometry(cfg)
     fe = cfg["fe"]
@@ -62,17 +64,17 @@ def fs_run(u0, cfg, dt, nsteps, record_every=0):
     k2 = k2_of(cfg)
     k4 = k2 * k2
     u = np.array(u0, dtype=np.float64)
-    uhat = _fft.fftn(u, axes)
+    uhat = _fft.fftn(u, axes, workers)
     snaps = [u.copy()] if record_every else None
     for step in range(nsteps):
         g = _fe.gradient(u, fe)
-        ghat = _fft.fftn(g, axes)
+        ghat = _fft.fftn(g, axes, workers)
         b_c = uhat[0] - M * dt * k2 * ghat[0]
         b_eta = uhat[1:] - L * dt * ghat[1:]
         uhat = np.empty_like(uhat)
         uhat[0] = b_c / (1.0 + M * dt * kc * k4)
         uhat[1:] = b_eta / (1.0 + L * dt * ke * k2)
-        u = _real(_fft.ifftn(uhat, axes), "state")
+        u = _real(_fft.ifftn(uhat, axes, workers), "state")
         if not np.all(np.isfinite(u)):
             raise FloatingPointError("FS run diverged at step %d" % (step + 1))
         if record_every and (step + 1) % record_every == 0:

@@ -2,8 +2,11 @@
 
 This module is shared by the HIP path's tests/benchmark and by the CPU
 oracle's tests.  It holds parameter values and initial-condition recipes
-only: none of the method's arithmetic (no free-energy derivatives, no
-transforms, no time stepping).
+only: none of the method's arithmetic (no free-energy derivatives, none of
+the step's transforms, no time stepping).  The one numerical step here is
+input preparation for the paper's study: moving fields between grids of the
+same box (subsampling, or band-limited interpolation through numpy.fft) and
+the Eq. (6) extrusion of 2D fields into a 3D initial state.
 
 A configuration is a plain dict:
     ndim      2 or 3
@@ -169,3 +172,44 @@ def workload_ic(cfg, w, seed=0):
     if w["ic"] == "paper":
         return paper_ic_2d(cfg)
     return random_ic(cfg, seed=seed, c0=w.get("c0", 0.5))
+
+
+# ---------------------------------------------------------------------------
+# The paper's study inputs (Sec. 2.1): fields moved between grids of one box,
+# and the 3D initial state of Eq. (6).
+
+def resample(u, n):
+    """Fields on an n x n grid from fields on an m x m grid of the same box:
+    every (m/n)-th point when coarser, Fourier zero-padding when finer."""
+    m = u.shape[-1]
+    if n <= m:
+        k = m // n
+        return np.ascontiguousarray(u[:, ::k, ::k])
+    U = np.fft.fft2(u, axes=(-2, -1))
+    out = np.zeros(u.shape[:-2] + (n, n), dtype=complex)
+    h = m // 2
+    out[..., :h, :h] = U[..., :h, :h]
+    out[..., :h, -h:] = U[..., :h, -h:]
+    out[..., -h:, :h] = U[..., -h:, :h]
+    out[..., -h:, -h:] = U[..., -h:, -h:]
+    return np.ascontiguousarray(np.real(np.fft.ifft2(out, axes=(-2, -1))) * (n * n) / (m * m))
+
+
+def extrude_3d(u2, n, c0=0.5, edge=100.0):
+    """Eq. (6): the order parameters of the 3D case from the 2D fields u2
+    ([F, m, m] on the 200 x 200 box) as
+        eta_i(x, y, z) = 0.5 {1 + tanh[atanh(2 eta_i^2D(2x, 2y) - 1)
+                                       - ((z - l_z / 2) / 5)^4]},
+    on an n^3 grid of the edge^3 box (x = j * edge / n); c = c0 everywhere.
+    (2x, 2y) falls on every (m / n)-th 2D grid point.  2 eta^2D - 1 is kept
+    inside (-1, 1) by 1e-12 so that atanh stays finite where a relaxed 2D
+    field sits at 0 or 1 to rounding."""
+    p = u2.shape[0] - 1
+    e2 = resample(u2[1:], n)                                # eta^2D(2x, 2y), [p, n, n]
+    a = np.arctanh(np.clip(2.0 * e2 - 1.0, -1.0 + 1e-12, 1.0 - 1e-12))
+    z = np.arange(n) * (edge / n)
+    dz4 = ((z - edge / 2) / 5.0) ** 4                       # [n]
+    u = np.empty((p + 1, n, n, n))
+    u[0] = c0
+    u[1:] = 0.5 * (1.0 + np.tanh(a[:, None, :, :] - dz4[None, :, None, None]))
+    return u

@@ -37,6 +37,7 @@ import time
 import numpy as np
 
 from . import inputs as I
+from .inputs import extrude_3d, resample  # noqa: F401  (the study's input preparation)
 
 DOMAIN = 200.0
 
@@ -58,23 +59,6 @@ def fd_stable_dt(n, safety=0.7):
     ch = 2.0 / (M * q * (4.0 + kc * q))
     ac = 2.0 / (L * (24.0 + ke * q))
     return safety * min(ch, ac)
-
-
-def resample(u, n):
-    """Fields on an n x n grid from fields on an m x m grid of the same box:
-    every (m/n)-th point when coarser, Fourier zero-padding when finer."""
-    m = u.shape[-1]
-    if n <= m:
-        k = m // n
-        return np.ascontiguousarray(u[:, ::k, ::k])
-    U = np.fft.fft2(u, axes=(-2, -1))
-    out = np.zeros(u.shape[:-2] + (n, n), dtype=complex)
-    h = m // 2
-    out[..., :h, :h] = U[..., :h, :h]
-    out[..., :h, -h:] = U[..., :h, -h:]
-    out[..., -h:, :h] = U[..., -h:, :h]
-    out[..., -h:, -h:] = U[..., -h:, -h:]
-    return np.ascontiguousarray(np.real(np.fft.ifft2(out, axes=(-2, -1))) * (n * n) / (m * m))
 
 
 def e_phi(ref, got):
@@ -207,26 +191,6 @@ TABLE2_FS_DT = 5e-3
 def paper_config_3d(n, kmode="spectral"):
     """The 3D case on an n^3 grid of the 100^3 box."""
     return I.make_config(3, n, DOMAIN3D / n, 4, I.PAPER_FE, kmode)
-
-
-def extrude_3d(u2, n, c0=0.5):
-    """Eq. (6): the order parameters of the 3D case from the 2D fields u2
-    ([F, m, m] on the 200 x 200 box) as
-        eta_i(x, y, z) = 0.5 {1 + tanh[atanh(2 eta_i^2D(2x, 2y) - 1)
-                                       - ((z - l_z / 2) / 5)^4]},
-    on an n^3 grid of the 100^3 box (x = j * 100 / n); c = c0 everywhere.
-    (2x, 2y) falls on every (m / n)-th 2D grid point.  2 eta^2D - 1 is kept
-    inside (-1, 1) by 1e-12 so that atanh stays finite where a relaxed 2D
-    field sits at 0 or 1 to rounding."""
-    p = u2.shape[0] - 1
-    e2 = resample(u2[1:], n)                                # eta^2D(2x, 2y), [p, n, n]
-    a = np.arctanh(np.clip(2.0 * e2 - 1.0, -1.0 + 1e-12, 1.0 - 1e-12))
-    z = np.arange(n) * (DOMAIN3D / n)
-    dz4 = ((z - DOMAIN3D / 2) / 5.0) ** 4                   # [n]
-    u = np.empty((p + 1, n, n, n))
-    u[0] = c0
-    u[1:] = 0.5 * (1.0 + np.tanh(a[:, None, :, :] - dz4[None, :, None, None]))
-    return u
 
 
 def run3d(grids, t0, t_end, methods, fd_grids, prec="f64", n_per=1024, log=_log, sink=None):

@@ -59,3 +59,17 @@ def test_impulse_and_shift_theorem():
 def test_rejects_non_power_of_two():
     with pytest.raises(ValueError):
         fft.fft_axis(np.ones(12), 0)
+
+
+def test_threaded_field_transforms_are_bit_identical():
+    # the per-field threads of fftn / ifftn / fs_run change no arithmetic
+    from oracle import fs
+    from paper_2306_04322_amd import inputs as I
+    rng = np.random.default_rng(11)
+    a = rng.random((5, 16, 32)) + 1j * rng.random((5, 16, 32))
+    assert np.array_equal(fft.fftn(a, (1, 2), workers=4), fft.fftn(a, (1, 2)))
+    assert np.array_equal(fft.ifftn(a, (1, 2), workers=3), fft.ifftn(a, (1, 2)))
+    for cfg in (I.make_config(2, (32, 16), 1.0, 4, I.PAPER_FE),
+                I.make_config(3, (8, 16, 8), 1.0, 2, I.PAPER_FE)):
+        u0 = I.random_ic(cfg, 3)
+        assert np.array_equal(fs.fs_run(u0, cfg, 0.1, 3, workers=5), fs.fs_run(u0, cfg, 0.1, 3))

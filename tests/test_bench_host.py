@@ -19,6 +19,24 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_algorithmic_bytes_of_the_two_passes():
+    """Per-stage bytes of the unfused method (each stage reads and writes its
+    F fields once; the update reads two sets): derivative 2Fs, forward FFT
+    2Fs, update 3Fs, inverse FFT 2Fs per point.  The row pass performs the
+    derivative and the x halves of both FFTs (4Fs), the column pass the
+    update and the y halves (5Fs); together the whole step's 9Fs."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2306_04322_amd import inputs as I
+    cfg, _ = I.workload_config("W2")
+    P = 1024 * 1024
+    assert bench.algorithmic_bytes(cfg, "f32", "row") == 4 * 5 * 4 * P
+    assert bench.algorithmic_bytes(cfg, "f32", "col") == 5 * 5 * 4 * P
+    assert bench.algorithmic_bytes(cfg, "f64", "step") == 9 * 5 * 8 * P
+    assert (bench.algorithmic_bytes(cfg, "f32", "row") + bench.algorithmic_bytes(cfg, "f32", "col")
+            == bench.algorithmic_bytes(cfg, "f32", "step"))
+
+
+def test_compulsory_bytes_of_the_two_passes():
     """Row pass: 2F half-spectra (F read, F written); column pass: 2F + 2
     (the carried c spectrum is read and written as well).  A half-spectrum
     of the 1024^2 FP32 grid is 1024 rows of 513 complex values of 8 bytes."""
@@ -27,8 +45,20 @@ def test_algorithmic_bytes_of_the_two_passes():
     from paper_2306_04322_amd import inputs as I
     cfg, _ = I.workload_config("W2")
     half = 1024 * 513 * 8
-    assert bench.algorithmic_bytes(cfg, "f32", "row") == 10 * half
-    assert bench.algorithmic_bytes(cfg, "f32", "col") == 12 * half
+    assert bench.compulsory_bytes(cfg, "f32", "row") == 10 * half
+    assert bench.compulsory_bytes(cfg, "f32", "col") == 12 * half
+
+
+def test_rel_l2_floor():
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    ref = np.stack([np.ones((4, 4)), np.zeros((4, 4))])
+    got = ref.copy()
+    got[0, 0, 0] += 0.4
+    e = bench.rel_l2(got, ref)
+    assert abs(e[0] - 0.1) < 1e-15 and e[1] is None
+    assert bench.max_err(e) == e[0]
 
 
 def test_committed_traffic_summary_matches_the_current_kernels():

@@ -123,6 +123,27 @@ pf_status pf_set_stream(pf_handle* h, void* stream);
  * PF_ERR_INVALID.  Asynchronous. */
 pf_status pf_step_fs(pf_handle* h, double dt, int64_t nsteps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * FS steps as pf_step_fs, on the field buffer `fields` (device, 256-byte
+ * aligned, layout and precision of the handle's config), with the step's
+ * workspace taken from a static device array of the library
+ * (PF_STATIC_SCRATCH_BYTES = 64 MiB, one copy per GPU, held from the
+ * library's load until the process exits) instead of a caller buffer.
+ * Needs no pf_bind and leaves the handle's binding untouched.  Allocates
+ * nothing: no hipMalloc, hipFree or allocating library call.  Runs on the
+ * current device; the first call on a device looks up the array's device
+ * address.  The tables are re-uploaded (hipMemcpyAsync from host memory
+ * the handle holds) on every call, and every workspace value the step reads
+ * is written earlier in the same call, so nothing carries over between
+ * calls.  All calls on one GPU share the one array: calls that overlap in
+ * time on one GPU (other streams, other threads) race and give wrong
+ * results.  PF_ERR_NOMEM if pf_workspace_bytes(h) exceeds the array;
+ * PF_ERR_INVALID for a NULL or unaligned `fields`, dt <= 0 or nsteps < 0.
+ * Asynchronous, like pf_step_fs. */
+#define PF_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+pf_status pf_step_fs_static(pf_handle* h, void* fields, double dt, int64_t nsteps);
+
 /* Advance the bound fields by nsteps explicit FD steps (Sec. 2.2: forward
  * Euler, 5-point (2D) / 7-point (3D) periodic Laplacian; every right-hand
  * side at time t), in place.  dt > 0 and nsteps >= 0, else PF_ERR_INVALID.

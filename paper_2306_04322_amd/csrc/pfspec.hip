@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -66,7 +67,46 @@ struct pf_handle {
   size_t prof_used = 0;
 };
 
+// Device scratch of pf_step_fs_static: the step's workspace (spectra,
+// tables, partial sums) for callers that cannot allocate device memory.  One
+// copy per GPU, held by the process from the library's load to its exit.
+// Host code must not pass `scratch` itself to a kernel or a copy: its host
+// name is a stand-in, not a device address.  The device address comes from
+// hipGetSymbolAddress, once per device (static_scratch_ptr).
+static constexpr size_t kStaticScratchBytes = PF_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device and kept.  NULL with a message in g_err on failure.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* static_scratch_ptr(std::string& why) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    why = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    why = "device index out of range";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
 
 int prof_begin(pf_handle* h, int cls) {
   if (!h->prof_on) return -1;
@@ -643,6 +683,8 @@ pf_status pf_create(const pf_config* cfg, pf_handle** out) {
   h->off_scal = off;
   off = align256(off + 64 * sizeof(double));
   h->ws_need = off;
+  if (h->es == 4) fill_staging<float>(h);
+  else fill_staging<double>(h);
   *out = h;
   return PF_OK;
 }
@@ -672,8 +714,6 @@ pf_status pf_bind(pf_handle* h, void* fields, void* workspace, size_t workspace_
     return fail(PF_ERR_NOMEM, "workspace too small: need " + std::to_string(h->ws_need) + " bytes");
   h->fields = fields;
   h->ws = static_cast<char*>(workspace);
-  if (h->es == 4) fill_staging<float>(h);
-  else fill_staging<double>(h);
   if (hipMemcpyAsync(h->ws + h->off_tw[0], h->staging.data(), h->staging.size(),
                      hipMemcpyHostToDevice, h->stream) != hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess)
@@ -715,6 +755,43 @@ pf_status pf_step_fs(pf_handle* h, double dt, int64_t nsteps) {
   }
   double* u = static_cast<double*>(h->fields);
   return fs_run<double>(h, dt, nsteps, u, u, nullptr);
+}
+
+pf_status pf_step_fs_static(pf_handle* h, void* fields, double dt, int64_t nsteps) {
+  if (!h) return fail(PF_ERR_INVALID, "handle is NULL");
+  if (!fields) return fail(PF_ERR_INVALID, "fields must be non-NULL");
+  if (reinterpret_cast<uintptr_t>(fields) & 255) return fail(PF_ERR_INVALID, "fields must be 256-byte aligned");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(PF_ERR_INVALID, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(PF_ERR_INVALID, "nsteps must be >= 0");
+  if (h->ws_need > kStaticScratchBytes)
+    return fail(PF_ERR_NOMEM, "pf_step_fs_static: the step needs " + std::to_string(h->ws_need) +
+                                  " bytes of workspace, above the static scratch of " +
+                                  std::to_string(kStaticScratchBytes) + " bytes");
+  std::string why;
+  char* ws = static_cast<char*>(static_scratch_ptr(why));
+  if (!ws) return fail(PF_ERR_HIP, why);
+  // the tables go in on every call: an earlier call on this device may have
+  // left another configuration's tables (or spectra) in the scratch
+  if (hipMemcpyAsync(ws + h->off_tw[0], h->staging.data(), h->staging.size(), hipMemcpyHostToDevice,
+                     h->stream) != hipSuccess)
+    return fail(PF_ERR_HIP, std::string("table upload: ") + hipGetErrorString(hipGetLastError()));
+  // run on the scratch, then restore the handle's own binding (if any)
+  char* const ws_bound = h->ws;
+  void* const fields_bound = h->fields;
+  h->ws = ws;
+  h->fields = fields;
+  h->last_dt = dt;
+  pf_status st;
+  if (h->es == 4) {
+    float* u = static_cast<float*>(fields);
+    st = fs_run<float>(h, dt, nsteps, u, u, nullptr);
+  } else {
+    double* u = static_cast<double*>(fields);
+    st = fs_run<double>(h, dt, nsteps, u, u, nullptr);
+  }
+  h->ws = ws_bound;
+  h->fields = fields_bound;
+  return st;
 }
 
 pf_status pf_step_fd(pf_handle* h, double dt, int64_t nsteps) {

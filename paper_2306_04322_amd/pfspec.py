@@ -23,6 +23,7 @@ PF_FE_POLY, PF_FE_PAPER = 0, 1
 PF_K_SPECTRAL, PF_K_FD2, PF_K_FD4 = 0, 1, 2
 KMODES = {"spectral": PF_K_SPECTRAL, "fd2": PF_K_FD2, "fd4": PF_K_FD4}
 PROF_ROW, PROF_COL, PROF_FD, PROF_RED, PROF_ADJ = range(5)
+PF_STATIC_SCRATCH_BYTES = 64 << 20  # include/pfspec.h
 
 
 class pf_config(ctypes.Structure):
@@ -47,6 +48,7 @@ _sig = {
     "pf_set_stream": (ctypes.c_int, [_H, _P]),
     "pf_step_fs": (ctypes.c_int, [_H, ctypes.c_double, ctypes.c_int64]),
     "pf_step_fd": (ctypes.c_int, [_H, ctypes.c_double, ctypes.c_int64]),
+    "pf_step_fs_static": (ctypes.c_int, [_H, _P, ctypes.c_double, ctypes.c_int64]),
     "pf_energy": (ctypes.c_int, [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "pf_adjoint_fs": (ctypes.c_int, [_H, ctypes.c_double, ctypes.c_int64, _P, _P,
                                      ctypes.POINTER(ctypes.c_double), _P]),
@@ -164,6 +166,10 @@ def pf_set_stream(h, stream):
 
 def pf_step_fs(h, dt, nsteps):
     _check(_lib.pf_step_fs(h, dt, nsteps), "pf_step_fs")
+
+
+def pf_step_fs_static(h, fields_ptr, dt, nsteps):
+    _check(_lib.pf_step_fs_static(h, fields_ptr, dt, nsteps), "pf_step_fs_static")
 
 
 def pf_step_fd(h, dt, nsteps):

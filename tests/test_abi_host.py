@@ -116,3 +116,22 @@ def test_workspace_and_segment_sizes(prec, es):
             assert ei.value.status == P.PF_ERR_INVALID
     finally:
         P.pf_destroy(h)
+
+
+def test_static_step_rejects_before_any_hip_call():
+    """pf_step_fs_static checks its arguments and the workspace size against
+    the static array before touching the GPU (the pointer is never used)."""
+    from paper_2306_04322_amd import pfspec as P
+    big = I.make_config(2, 2048, 1.0, 4, I.PAPER_FE)
+    h = P.pf_create(P.make_config(big, "f64"))
+    try:
+        assert P.pf_workspace_bytes(h) > P.PF_STATIC_SCRATCH_BYTES
+        with pytest.raises(P.PFError) as ei:
+            P.pf_step_fs_static(h, 256, 0.1, 1)
+        assert ei.value.status == P.PF_ERR_NOMEM
+        for args in ((0, 0.1, 1), (128, 0.1, 1), (256, 0.0, 1), (256, 0.1, -1)):
+            with pytest.raises(P.PFError) as ei:
+                P.pf_step_fs_static(h, *args)
+            assert ei.value.status == P.PF_ERR_INVALID
+    finally:
+        P.pf_destroy(h)

@@ -31,23 +31,33 @@ __device__ __forceinline__ void fe_grad(const FeParams<T>& P, int p_rt, T c, con
   for (int i = 0; i < PMAX; ++i)
     if (i < p) s2 += eta[i] * eta[i];
   if (kind == FE_PAPER) {
+    // f_chem = rho2 (c-ca)^2 (1-H) + rho2 (cb-c)^2 H + w g, H = sum h(eta_i):
+    //   df/dc      = 2 rho2 (c - ca) - 2 rho2 (cb - ca) H
+    //   df/deta_i  = J h'(e) + w [2 e (1-e)(1-2e) + 4 alpha e (s2 - e^2)]
+    // with J = rho2 [(cb-c)^2 - (c-ca)^2] = rho2 (cb-ca)(cb+ca-2c),
+    // h(e) = e^3 (6e^2 - 15e + 10), h'(e) = 30 e^2 (1-e)^2.  Factored as
+    //   df/deta_i = e { (1-e) [30 J e (1-e) + 2w - 4w e] + 4 w alpha (s2 - e^2) }
+    // so every term keeps its factors of e and 1 - e (no cancellation near
+    // e = 0 or 1) with about half the operations of the expanded form.
     const T rho2 = P.k[0], ca = P.k[1], cb = P.k[2], w = P.k[3], al = P.k[4];
+    const T dcb = cb - ca;
     T H = T(0);
 #pragma unroll
     for (int i = 0; i < PMAX; ++i)
       if (i < p) {
         const T e = eta[i];
-        H += e * e * e * (T(6) * e * e - T(15) * e + T(10));
+        H += (e * e * e) * ((T(6) * e - T(15)) * e + T(10));
       }
-    gc = T(2) * rho2 * ((c - ca) - (cb - ca) * H);
-    const T jump = rho2 * ((cb - c) * (cb - c) - (c - ca) * (c - ca));
+    gc = T(2) * rho2 * ((c - ca) - dcb * H);
+    const T A = T(30) * rho2 * dcb * ((cb + ca) - T(2) * c);  // 30 J
+    const T w2 = T(2) * w, w4 = T(4) * w, wa4 = T(4) * w * al;
 #pragma unroll
     for (int i = 0; i < PMAX; ++i)
       if (i < p) {
         const T e = eta[i];
         const T om = T(1) - e;
-        ge[i] = jump * (T(30) * e * e * om * om) +
-                w * (T(2) * e * om * (T(1) - T(2) * e) + T(4) * al * e * (s2 - e * e));
+        const T inner = (A * e) * om + (w2 - w4 * e);
+        ge[i] = e * (om * inner + wa4 * (s2 - e * e));
       }
   } else {
     const T ca = P.k[0], cb = P.k[1], cm = P.k[2], A = P.k[3], B = P.k[4], D = P.k[5];

@@ -77,7 +77,8 @@ enum {
   X_FWD_DERIV = 4,   // R2C of [df/dc, eta_i - dt L df/deta_i] -> b_out fields 1..F
   X_FWD_RAW = 8,     // R2C of the F real rows as they are -> b_out
   X_ESUM = 16,       // double sums of f(u) and c -> partials[block][2]
-  X_WITH_C = 32      // with X_FWD_DERIV: also R2C of c -> b_out field 0
+  X_WITH_C = 32,     // with X_FWD_DERIV: also R2C of c -> b_out field 0
+  X_CSUM = 64        // double sum of c only -> partials[block][1] ([0] = 0)
 };
 
 // 1 / x for the k-space multipliers (x >= 1).  float: the hardware
@@ -217,18 +218,20 @@ xpass_kernel(XArgs<T> a) {
       }
   }
 
-  if (a.flags & X_ESUM) {
+  if (a.flags & (X_ESUM | X_CSUM)) {
     double acc[2] = {0.0, 0.0};
     if (active) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          T eta[PMAX];
-#pragma unroll
-          for (int i = 0; i < PMAX; ++i) eta[i] = (i < p) ? (h ? u[1 + i][m].y : u[1 + i][m].x) : T(0);
           const T c = h ? u[0][m].y : u[0][m].x;
-          acc[0] += fe_density<T, PMAX>(a.fe, p, c, eta);
+          if (a.flags & X_ESUM) {
+            T eta[PMAX];
+#pragma unroll
+            for (int i = 0; i < PMAX; ++i) eta[i] = (i < p) ? (h ? u[1 + i][m].y : u[1 + i][m].x) : T(0);
+            acc[0] += fe_density<T, PMAX>(a.fe, p, c, eta);
+          }
           acc[1] += double(c);
         }
       }
@@ -456,10 +459,8 @@ rowpass_kernel(XArgs<T> a) {
         T e[PMAX];
 #pragma unroll
         for (int i = 0; i < PMAX; ++i) e[i] = h ? eta[i].y : eta[i].x;
-        if (flags & X_ESUM) {
-          acc[0] += fe_density<T, PMAX>(a.fe, pp, ch, e);
-          acc[1] += double(ch);
-        }
+        if (flags & X_ESUM) acc[0] += fe_density<T, PMAX>(a.fe, pp, ch, e);
+        if (flags & (X_ESUM | X_CSUM)) acc[1] += double(ch);
         if (flags & X_FWD_DERIV) {
           T gc, ge[PMAX];
 #pragma unroll
@@ -476,7 +477,7 @@ rowpass_kernel(XArgs<T> a) {
       }
     }
   }
-  if (flags & X_ESUM) {
+  if (flags & (X_ESUM | X_CSUM)) {
     block_sum<2>(acc, red);
     if (tid == 0) {
       a.partials[2 * blockIdx.x + 0] = acc[0];

@@ -319,7 +319,7 @@ pf_status fs_run(pf_handle* h, double dt, long long nsteps, const T* uin, T* uou
   x.dtL = T(dt * h->L);
   x.u_in = uin;
   x.b_out = specB<T>(h);
-  x.flags = X_LOAD_REAL | X_FWD_DERIV | X_WITH_C | X_ESUM;
+  x.flags = X_LOAD_REAL | X_FWD_DERIV | X_WITH_C | X_CSUM;
   int nb = 0;
   PF_TRY(row<T>(h, x, &nb));
   PF_TRY(reduce(h, nb, 2, scal(h) + SC_FSUM, 1.0, 1.0 / double(h->P), 0, 0));

@@ -12,8 +12,9 @@
 // on grids whose neighbour rows or planes fit in L2, each XCD takes a
 // contiguous band of the grid so those re-reads stay in its own L2.  On
 // larger 3D grids each thread instead marches along z over a few planes and
-// keeps its neighbour planes in registers.  The energy kernel keeps one
-// thread per point.
+// keeps its neighbour planes in registers, and a work-group stages the
+// current plane of its rows (plus one halo row on each side) in LDS for the
+// y and x neighbours.  The energy kernel keeps one thread per point.
 // Periodic wrap uses power-of-two masks instead of ghost layers.
 #include "pf_kernels.h"
 #include "pf_launch.h"
@@ -65,6 +66,22 @@ __device__ __forceinline__ void st_vec(T* p, const T* v) {
 #pragma unroll
   for (int k = 0; k < V; ++k) w.v[k] = v[k];
   *reinterpret_cast<FdVec<T, V>*>(p) = w;
+}
+
+// The same store with the non-temporal hint: the marching kernels write
+// their outputs once and never read them back, so the stores should not
+// displace the neighbour planes the kernel re-reads from L2.
+template <typename T, int V>
+__device__ __forceinline__ void st_vec_nt(T* p, const T* v) {
+  if constexpr (V == 1) {
+    __builtin_nontemporal_store(v[0], p);
+  } else {
+    typedef T vt __attribute__((ext_vector_type(V)));
+    vt w;
+#pragma unroll
+    for (int k = 0; k < V; ++k) w[k] = v[k];
+    __builtin_nontemporal_store(w, reinterpret_cast<vt*>(p));
+  }
 }
 
 // Neighbour offsets of the vector starting at point i0 (x0 = i0 mod nx, a
@@ -217,11 +234,17 @@ struct ZCol {
   int x0, z0;
 };
 
+// Work-groups are dealt to the eight XCDs round-robin; block b is mapped to
+// the logical block of XCD b % 8's contiguous eighth of the grid (the launch
+// rounds the group count up to a multiple of 8), so the groups of one z
+// block that hold y-adjacent rows run on one XCD and find each other's rows
+// (their y neighbours) in that XCD's L2.
 template <typename T, int V>
 __device__ __forceinline__ bool zcol(const FdArgs<T>& a, int zb, ZCol& q) {
   const long long nxv = a.nx / V;
   const long long per = nxv * a.ny;  // vectors per plane
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned b = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const long long t = (long long)b * blockDim.x + threadIdx.x;
   if (t >= per * (a.nz / zb)) return false;
   const long long vin = t % per;
   q.z0 = int(t / per) * zb;
@@ -274,7 +297,7 @@ __global__ void __launch_bounds__(256) fd_mu_z_kernel(FdArgs<T> a, int zb) {
     lap_vec_z<T, V>(a.in, m[0], c[0], n[0], row, q.x0, zoff + q.ymr, zoff + q.ypr, a, l);
 #pragma unroll
     for (int e = 0; e < V; ++e) o[e] = gc[e] - a.kc * l[e];
-    st_vec<T, V>(a.mu + i0, o);
+    st_vec_nt<T, V>(a.mu + i0, o);
 #pragma unroll
     for (int j = 0; j < PMAX; ++j)
       if (j < p) {
@@ -282,7 +305,7 @@ __global__ void __launch_bounds__(256) fd_mu_z_kernel(FdArgs<T> a, int zb) {
         lap_vec_z<T, V>(ev, m[j + 1], c[j + 1], n[j + 1], row, q.x0, zoff + q.ymr, zoff + q.ypr, a, l);
 #pragma unroll
         for (int e = 0; e < V; ++e) o[e] = c[j + 1].v[e] - a.dtL * (ge[j][e] - a.ke * l[e]);
-        st_vec<T, V>(a.out + (j + 1) * a.P + i0, o);
+        st_vec_nt<T, V>(a.out + (j + 1) * a.P + i0, o);
       }
 #pragma unroll
     for (int f = 0; f <= PMAX; ++f) {
@@ -308,7 +331,175 @@ __global__ void __launch_bounds__(256) fd_c_z_kernel(FdArgs<T> a, int zb) {
     lap_vec_z<T, V>(a.mu, m, c, n, zoff + (q.rest - q.x0), q.x0, zoff + q.ymr, zoff + q.ypr, a, l);
 #pragma unroll
     for (int e = 0; e < V; ++e) o[e] = cu.v[e] + a.dtM * l[e];
-    st_vec<T, V>(a.out + i0, o);
+    st_vec_nt<T, V>(a.out + i0, o);
+    m = c;
+    c = n;
+  }
+}
+
+// Marching kernels with the current plane staged in LDS.  A work-group of
+// FD_ZL_WG threads owns a tile of R = FD_ZL_WG V / nx consecutive y rows
+// (one vector per thread) of one block of planes; per plane it writes its
+// centre vectors (kept in registers from the previous plane, as above) and
+// the two halo rows y0 - 1 and y0 + R of every field it differentiates into
+// LDS, and takes the y and x neighbours from there.  Each field is then
+// read about (R + 2) / R times per step instead of once per neighbour row.
+// Same arithmetic, in the same order, as the other FD step kernels.
+constexpr int FD_ZL_WG = 512;
+
+template <typename T, int V>
+__device__ __forceinline__ void lap_lds(const T* __restrict__ tile, int r, int x0, int nx,
+                                        const FdVec<T, V>& zm, const FdVec<T, V>& cv,
+                                        const FdVec<T, V>& zp, const FdArgs<T>& a, T* out) {
+  // tile rows: 0 = y0 - 1, 1..R = own rows, R + 1 = y0 + R
+  const T* up = tile + (long long)r * nx;        // row y - 1
+  const T* dn = tile + (long long)(r + 2) * nx;  // row y + 1
+  const T* me = tile + (long long)(r + 1) * nx;
+  const FdVec<T, V> vm = *reinterpret_cast<const FdVec<T, V>*>(up + x0);
+  const FdVec<T, V> vp = *reinterpret_cast<const FdVec<T, V>*>(dn + x0);
+  const T xl = me[(x0 - 1) & (nx - 1)], xr = me[(x0 + V) & (nx - 1)];
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    const T c = cv.v[k];
+    const T left = k == 0 ? xl : cv.v[k - 1];
+    const T right = k == V - 1 ? xr : cv.v[k + 1];
+    T rr = (right - T(2) * c + left) * a.ix2 + (vp.v[k] - T(2) * c + vm.v[k]) * a.iy2;
+    rr += (zp.v[k] - T(2) * c + zm.v[k]) * a.iz2;
+    out[k] = rr;
+  }
+}
+
+// Tile of this work-group: first row y0, first plane z0, and this thread's
+// row r within the tile and x0.  Blocks are mapped to XCD-contiguous eighths
+// of the grid as in zcol, so neighbouring tiles share an L2.
+struct ZTile {
+  long long plane;
+  int y0, z0, r, x0, R;
+};
+
+template <typename T, int V>
+__device__ __forceinline__ bool ztile(const FdArgs<T>& a, int zb, ZTile& q) {
+  const int tpr = a.nx / V;  // threads per row
+  q.R = FD_ZL_WG / tpr;
+  const int tiles = a.ny / q.R;
+  const unsigned b = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  if ((long long)b >= (long long)tiles * (a.nz / zb)) return false;
+  q.y0 = int(b % tiles) * q.R;
+  q.z0 = int(b / tiles) * zb;
+  q.r = threadIdx.x / tpr;
+  q.x0 = int(threadIdx.x - q.r * tpr) * V;
+  q.plane = (long long)a.nx * a.ny;
+  return true;
+}
+
+// Stage plane z of `nf` fields (field stride fs from base) into LDS: the
+// centre vectors from registers, the halo rows from memory (threads of the
+// first two rows of the tile load them).
+template <typename T, int V, int NF>
+__device__ __forceinline__ void stage_plane(T* lds, const T* __restrict__ base, long long fs,
+                                            const FdVec<T, V>* cv, int nf, int z,
+                                            const ZTile& q, const FdArgs<T>& a) {
+  const int tsz = (q.R + 2) * a.nx;  // LDS values per field
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+    if (f < nf)
+      *reinterpret_cast<FdVec<T, V>*>(lds + f * tsz + (q.r + 1) * a.nx + q.x0) = cv[f];
+  if (q.r < 2) {
+    const int yh = q.r == 0 ? ((q.y0 - 1) & (a.ny - 1)) : ((q.y0 + q.R) & (a.ny - 1));
+    const int lr = q.r == 0 ? 0 : q.R + 1;
+    const long long off = (long long)z * q.plane + (long long)yh * a.nx + q.x0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+      if (f < nf)
+        *reinterpret_cast<FdVec<T, V>*>(lds + f * tsz + lr * a.nx + q.x0) =
+            ld_vec<T, V>(base + f * fs + off);
+  }
+}
+
+template <typename T, int PMAX, int V>
+__global__ void __launch_bounds__(FD_ZL_WG) fd_mu_zl_kernel(FdArgs<T> a, int zb) {
+  extern __shared__ __align__(16) unsigned char fd_lds_raw[];
+  T* lds = reinterpret_cast<T*>(fd_lds_raw);
+  ZTile q;
+  if (!ztile<T, V>(a, zb, q)) return;
+  const int p = a.F - 1;
+  const int tsz = (q.R + 2) * a.nx;
+  const long long rest = (long long)(q.y0 + q.r) * a.nx + q.x0;
+  FdVec<T, V> m[PMAX + 1], c[PMAX + 1], n[PMAX + 1];
+  const long long zm0 = (long long)((q.z0 - 1) & (a.nz - 1)) * q.plane + rest;
+  const long long zc0 = (long long)q.z0 * q.plane + rest;
+#pragma unroll
+  for (int f = 0; f <= PMAX; ++f)
+    if (f <= p) {
+      m[f] = ld_vec<T, V>(a.in + f * a.P + zm0);
+      c[f] = ld_vec<T, V>(a.in + f * a.P + zc0);
+    }
+  for (int k = 0; k < zb; ++k) {
+    const int z = q.z0 + k;
+    const long long i0 = (long long)z * q.plane + rest;
+    const long long zn = (long long)((z + 1) & (a.nz - 1)) * q.plane + rest;
+#pragma unroll
+    for (int f = 0; f <= PMAX; ++f)
+      if (f <= p) n[f] = ld_vec<T, V>(a.in + f * a.P + zn);
+    stage_plane<T, V, PMAX + 1>(lds, a.in, a.P, c, p + 1, z, q, a);
+    __syncthreads();
+    T gc[V], ge[PMAX][V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      T eta[PMAX], g[PMAX];
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j) {
+        eta[j] = (j < p) ? c[j + 1].v[e] : T(0);
+        g[j] = T(0);
+      }
+      fe_grad<T, PMAX>(a.fe, p, c[0].v[e], eta, gc[e], g);
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j) ge[j][e] = g[j];
+    }
+    T l[V], o[V];
+    lap_lds<T, V>(lds, q.r, q.x0, a.nx, m[0], c[0], n[0], a, l);
+#pragma unroll
+    for (int e = 0; e < V; ++e) o[e] = gc[e] - a.kc * l[e];
+    st_vec_nt<T, V>(a.mu + i0, o);
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j)
+      if (j < p) {
+        lap_lds<T, V>(lds + (j + 1) * tsz, q.r, q.x0, a.nx, m[j + 1], c[j + 1], n[j + 1], a, l);
+#pragma unroll
+        for (int e = 0; e < V; ++e) o[e] = c[j + 1].v[e] - a.dtL * (ge[j][e] - a.ke * l[e]);
+        st_vec_nt<T, V>(a.out + (j + 1) * a.P + i0, o);
+      }
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f <= PMAX; ++f) {
+      m[f] = c[f];
+      c[f] = n[f];
+    }
+  }
+}
+
+template <typename T, int V>
+__global__ void __launch_bounds__(FD_ZL_WG) fd_c_zl_kernel(FdArgs<T> a, int zb) {
+  extern __shared__ __align__(16) unsigned char fd_lds_raw[];
+  T* lds = reinterpret_cast<T*>(fd_lds_raw);
+  ZTile q;
+  if (!ztile<T, V>(a, zb, q)) return;
+  const long long rest = (long long)(q.y0 + q.r) * a.nx + q.x0;
+  FdVec<T, V> m = ld_vec<T, V>(a.mu + (long long)((q.z0 - 1) & (a.nz - 1)) * q.plane + rest);
+  FdVec<T, V> c = ld_vec<T, V>(a.mu + (long long)q.z0 * q.plane + rest);
+  for (int k = 0; k < zb; ++k) {
+    const int z = q.z0 + k;
+    const long long i0 = (long long)z * q.plane + rest;
+    const FdVec<T, V> n = ld_vec<T, V>(a.mu + (long long)((z + 1) & (a.nz - 1)) * q.plane + rest);
+    const FdVec<T, V> cu = ld_vec<T, V>(a.in + i0);
+    stage_plane<T, V, 1>(lds, a.mu, 0, &c, 1, z, q, a);
+    __syncthreads();
+    T l[V], o[V];
+    lap_lds<T, V>(lds, q.r, q.x0, a.nx, m, c, n, a, l);
+#pragma unroll
+    for (int e = 0; e < V; ++e) o[e] = cu.v[e] + a.dtM * l[e];
+    st_vec_nt<T, V>(a.out + i0, o);
+    __syncthreads();
     m = c;
     c = n;
   }
@@ -363,6 +554,9 @@ static int fd_vec_width(long long P) {
 #ifndef PF_FD_ZMARCH
 #define PF_FD_ZMARCH 1  // 3D grids without bands: threads march along z
 #endif
+#ifndef PF_FD_ZLDS
+#define PF_FD_ZLDS 1  // marching kernels with the current plane staged in LDS
+#endif
 #ifndef PF_FD_ZB
 #define PF_FD_ZB 8  // planes per marching thread
 #endif
@@ -383,7 +577,25 @@ static int fd_go_v(int which, const FdArgs<T>& a, hipStream_t s) {
   const int bands = fd_bands(a);
   if (PF_FD_ZMARCH && a.ndim == 3 && !bands) {
     const int zb = a.nz < PF_FD_ZB ? a.nz : PF_FD_ZB;  // both powers of two
-    const int grid = int((nv / zb + 255) / 256);
+    // LDS-staged form: tiles of R >= 2 rows that divide Ny, with the plane
+    // tiles of all F fields small enough for three work-groups per compute
+    // unit (160 KiB of LDS); with fewer (FP64, F = 5, 256-point rows: two)
+    // the register form was measured faster (3D 256^3 FD step 0.43 against
+    // 0.39 ms)
+    const int tpr = a.nx / V;
+    const int R = tpr <= FD_ZL_WG ? FD_ZL_WG / tpr : 0;
+    const size_t lds_mu = size_t(a.F) * (R + 2) * a.nx * sizeof(T);
+    if (PF_FD_ZLDS && R >= 2 && R <= a.ny && lds_mu <= (160u << 10) / 3) {
+      const long long nb = (long long)(a.ny / R) * (a.nz / zb);
+      const int grid = int((nb + 7) / 8 * 8);
+      if (which == 0)
+        hipLaunchKernelGGL((fd_mu_zl_kernel<T, PMAX, V>), dim3(grid), dim3(FD_ZL_WG), lds_mu, s, a, zb);
+      else
+        hipLaunchKernelGGL((fd_c_zl_kernel<T, V>), dim3(grid), dim3(FD_ZL_WG),
+                           size_t(R + 2) * a.nx * sizeof(T), s, a, zb);
+      return grid;
+    }
+    const int grid = int((nv / zb + 255) / 256 + 7) / 8 * 8;
     if (which == 0) hipLaunchKernelGGL((fd_mu_z_kernel<T, PMAX, V>), dim3(grid), dim3(256), 0, s, a, zb);
     else hipLaunchKernelGGL((fd_c_z_kernel<T, V>), dim3(grid), dim3(256), 0, s, a, zb);
     return grid;

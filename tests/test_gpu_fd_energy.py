@@ -56,6 +56,10 @@ def test_fd_workload_parity(prec):
                                       # thread (FP64; in FP32 these planes take XCD bands)
                                       (3, (256, 256, 32), 4), (3, (256, 256, 16), 2),
                                       (3, (128, 128, 8), 8),
+                                      # the marching form with the current plane in
+                                      # LDS: tiles of 8 (FP32) / 4 (FP64) rows above,
+                                      # two-row tiles here in FP32 (FP64: registers)
+                                      (3, (1024, 128, 8), 1),
                                       # longest axes
                                       (2, (4096, 8), 1), (2, (8, 4096), 2), (3, (8, 8, 1024), 2)])
 def test_fd_shapes_parity(ndim, n, p, prec):

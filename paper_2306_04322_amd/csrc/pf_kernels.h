@@ -2,11 +2,18 @@
 //
 // Data layout in HBM (complex values interleaved re/im):
 //   real fields   [F][Nz][Ny][Nx]            element type T
-//   x-spectra     [G][Nz][Ny][Sx]            c2<T>, row r holds the real-to-
-//                                            complex transform along x of
-//                                            row r: Nx/2 + 1 values, padded
-//                                            to the 128-byte row stride Sx
-// A "row" is one (z, y) line along x; rows = Ny * Nz.
+//   x-spectra     [G][Nz][Ny][Sx] + [G][Nz][Ny] c2<T>: row r holds the
+//                                            real-to-complex transform along x
+//                                            of row r, values kx = 0 .. Nx/2 - 1
+//                                            at row stride Sx (128-byte
+//                                            multiple); the Nyquist values
+//                                            kx = Nx/2 of all rows follow as one
+//                                            array (offset nyo in the field),
+//                                            contiguous along y
+// A "row" is one (z, y) line along x; rows = Ny * Nz.  Keeping the Nyquist
+// column apart lets the strided passes cover kx < Nx/2 with full tiles and
+// the Nyquist column with a few items that take many outer rows at once
+// (in 3D a 16-column tile of it alone cost one work item in nine).
 //
 // Row pass: transforms along the contiguous x axis.  Depending on `flags`
 // it loads real rows or inverse-transforms x-spectra back to real rows
@@ -100,10 +107,52 @@ struct XArgs {
   double* partials;
   long long fs_real;  // field stride of real arrays (elements)
   long long fs_spec;  // field stride of x-spectra (complex elements)
+  long long nyo;      // offset of the Nyquist values within an x-spectrum field
   int rows, Sx, F, flags;
   FeParams<T> fe;
   T dtL;
+  // optional in-kernel finish of the double sums (X_ESUM / X_CSUM): when
+  // sum_count is set, the last work-group to finish adds up every group's
+  // record in a fixed order and writes sum_out[i] = sum_scale[i] * total[i]
+  unsigned* sum_count;
+  double* sum_out;
+  double sum_scale[2];
 };
+
+// Fixed-order finish of per-work-group double records: called by every
+// thread of every work-group after thread 0 has written the group's record
+// partials[blockIdx.x * NV + i].  The last group to arrive (counted on
+// *count, which must be 0 at launch and is reset to 0 here) sums all
+// gridDim.x records, each thread a fixed strided subset, then the fixed
+// work-group reduction, so the result does not depend on which group is
+// last or on timing.
+template <int NV>
+__device__ __forceinline__ void finish_sums(const double* partials, unsigned* count, double* out,
+                                            const double* scale, double* red) {
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+    __threadfence();  // this group's record before the count
+    const unsigned prev = atomicAdd(count, 1u);
+    is_last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (is_last) {  // uniform across the work-group
+    __threadfence();  // every group's record after the count
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (unsigned r = threadIdx.x; r < gridDim.x; r += blockDim.x) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += partials[(long long)r * NV + i];
+    }
+    block_sum<NV>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) out[i] = acc[i] * scale[i];
+      *count = 0u;
+    }
+  }
+}
 
 // Row pass geometry for a real length NX.
 template <typename T, int NX, int PMAX>
@@ -117,11 +166,13 @@ struct XGeom {
   static constexpr int REGION = lds_span(NH) + 1;  // LDS complex values per team
 };
 
-// C2R of one row: x-spectrum src[0..NH] -> v[m] = (x[2k], x[2k+1]),
+// C2R of one row: x-spectrum src[0..NH-1] and its Nyquist value *nyq ->
+// v[m] = (x[2k], x[2k+1]),
 // k = t + TEAM m, with x the unnormalised inverse over the Hermitian
 // extension (x_j = sum_k X_k exp(+2 pi i j k / NX)).
 template <typename T, int NX, int E>
-__device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src, bool active,
+__device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src,
+                                        const c2<T>* __restrict__ nyq, bool active,
                                         int t, c2<T>* my, const LaneTwiddles<T, NX / 2, E>& lt,
                                         const Twiddles<T, NX / 2, E>& tws) {
   constexpr int NH = NX / 2;
@@ -131,7 +182,7 @@ __device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src,
   for (int m = 0; m < E; ++m) X[m] = active ? src[t + TEAM * m] : mk<T>(T(0), T(0));
 #pragma unroll
   for (int m = 0; m < E; ++m) my[t + TEAM * m] = X[m];
-  if (t == 0) my[NH] = active ? src[NH] : mk<T>(T(0), T(0));
+  if (t == 0) my[NH] = active ? *nyq : mk<T>(T(0), T(0));
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -145,9 +196,11 @@ __device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src,
   team_fft<T, NH, E, true, 1>(v, t, my, tws);
 }
 
-// R2C of one row held as v[m] = (x[2k], x[2k+1]); writes X[0..NH] to dst.
+// R2C of one row held as v[m] = (x[2k], x[2k+1]); writes X[0..NH-1] to dst
+// and X[NH] to *nyq.
 template <typename T, int NX, int E>
-__device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* __restrict__ dst, bool active, int t,
+__device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* __restrict__ dst, c2<T>* __restrict__ nyq,
+                                        bool active, int t,
                                         c2<T>* my, const LaneTwiddles<T, NX / 2, E>& lt,
                                         const Twiddles<T, NX / 2, E>& tws) {
   constexpr int NH = NX / 2;
@@ -166,7 +219,7 @@ __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* __restrict__ dst, bool 
     const c2<T> B2 = mk<T>(d.y, -d.x);  // 2 B_k
     const c2<T> WB = cmul<T>(B2, lt.w[m]);
     if (active) dst[k] = mk<T>(T(0.5) * (s.x + WB.x), T(0.5) * (s.y + WB.y));
-    if (k == 0 && active) dst[NH] = mk<T>(T(0.5) * (s.x - B2.x), T(0.5) * (s.y - B2.y));
+    if (k == 0 && active) *nyq = mk<T>(T(0.5) * (s.x - B2.x), T(0.5) * (s.y - B2.y));
   }
   __syncthreads();
 }
@@ -205,7 +258,9 @@ xpass_kernel(XArgs<T> a) {
   } else {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
-      if (f < F) row_c2r<T, NX, E>(u[f], a.s_in + f * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
+      if (f < F)
+        row_c2r<T, NX, E>(u[f], a.s_in + f * a.fs_spec + rrow * a.Sx, a.s_in + f * a.fs_spec + a.nyo + rrow,
+                          active, t, my, lt, tws);
   }
 
   if ((a.flags & X_STORE_REAL) && active) {
@@ -241,6 +296,7 @@ xpass_kernel(XArgs<T> a) {
       a.partials[2 * blockIdx.x + 0] = acc[0];
       a.partials[2 * blockIdx.x + 1] = acc[1];
     }
+    if (a.sum_count) finish_sums<2>(a.partials, a.sum_count, a.sum_out, a.sum_scale, red);
   }
 
   if (a.flags & X_FWD_DERIV) {
@@ -271,20 +327,25 @@ xpass_kernel(XArgs<T> a) {
       gcv[m] = mk<T>(gcx, gcy);
     }
     if (a.flags & X_WITH_C)
-      row_r2c<T, NX, E>(u[0], a.b_out + 0 * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
-    row_r2c<T, NX, E>(gcv, a.b_out + 1 * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
+      row_r2c<T, NX, E>(u[0], a.b_out + rrow * a.Sx, a.b_out + a.nyo + rrow, active, t, my, lt, tws);
+    row_r2c<T, NX, E>(gcv, a.b_out + 1 * a.fs_spec + rrow * a.Sx, a.b_out + 1 * a.fs_spec + a.nyo + rrow,
+                      active, t, my, lt, tws);
 #pragma unroll
     for (int i = 0; i < PMAX; ++i)
-      if (i < p) row_r2c<T, NX, E>(u[1 + i], a.b_out + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
+      if (i < p)
+        row_r2c<T, NX, E>(u[1 + i], a.b_out + (2 + i) * a.fs_spec + rrow * a.Sx,
+                          a.b_out + (2 + i) * a.fs_spec + a.nyo + rrow, active, t, my, lt, tws);
   } else if (a.flags & X_FWD_RAW) {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
-      if (f < F) row_r2c<T, NX, E>(u[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
+      if (f < F)
+        row_r2c<T, NX, E>(u[f], a.b_out + f * a.fs_spec + rrow * a.Sx, a.b_out + f * a.fs_spec + a.nyo + rrow,
+                          active, t, my, lt, tws);
   }
 }
 
 // Input half of a C2R by one wavefront team: pairs each X_k of the
-// x-spectrum row src[0..NH] with conj(X_{NH-k}) and leaves in v[m] the
+// x-spectrum row (src[0..NH-1], X_NH = *nyq) with conj(X_{NH-k}) and leaves in v[m] the
 // complex sequence whose length-NH inverse FFT gives the real row as pairs
 // (x[2k], x[2k+1]), k = t + TEAM m.  `lt` holds exp(-2 pi i k / (2 NH)).
 // float rows of Nx <= 512 (several teams per wavefront): the row is read
@@ -293,7 +354,8 @@ xpass_kernel(XArgs<T> a) {
 // wavefront per SIMD on 256-point rows); otherwise both reads come from
 // global memory (measured faster where occupancy does not change).
 template <typename T, int NH, int E>
-__device__ __forceinline__ void wave_c2r_pre(c2<T>* v, const c2<T>* __restrict__ src, c2<T>* ar,
+__device__ __forceinline__ void wave_c2r_pre(c2<T>* v, const c2<T>* __restrict__ src,
+                                             const c2<T>* __restrict__ nyq, c2<T>* ar,
                                              int t, const LaneTwiddles<T, NH, E>& lt) {
   constexpr int TEAM = NH / E;
   constexpr bool STAGE = sizeof(T) == 4 && TEAM < 64;
@@ -301,7 +363,7 @@ __device__ __forceinline__ void wave_c2r_pre(c2<T>* v, const c2<T>* __restrict__
 #pragma unroll
   for (int m = 0; m < E; ++m) X[m] = src[t + TEAM * m];
   if constexpr (STAGE) {
-    const c2<T> xn = src[t == 0 ? NH : 0];
+    const c2<T> xn = t == 0 ? *nyq : src[0];
 #pragma unroll
     for (int m = 0; m < E; ++m) ar[pad(t + TEAM * m)] = X[m];
     if (t == 0) ar[pad(NH)] = xn;
@@ -310,7 +372,7 @@ __device__ __forceinline__ void wave_c2r_pre(c2<T>* v, const c2<T>* __restrict__
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + TEAM * m;
-    const c2<T> Y = conj<T>(STAGE ? ar[pad(NH - k)] : src[NH - k]);
+    const c2<T> Y = conj<T>(STAGE ? ar[pad(NH - k)] : (k == 0 ? *nyq : src[(NH - k) & (NH - 1)]));
     const c2<T> sm = add<T>(X[m], Y);
     const c2<T> d = cmulc<T>(sub<T>(X[m], Y), lt.w[m]);  // * exp(+2 pi i k / NX)
     v[m] = mk<T>(sm.x - d.y, sm.y + d.x);
@@ -420,9 +482,10 @@ rowpass_kernel(XArgs<T> a) {
       const int f = j - r * F;
       if (j < njobs && row0 + r < a.rows) {
         const c2<T>* src = a.s_in + f * a.fs_spec + (long long)(row0 + r) * a.Sx;
+        const c2<T>* nyq = a.s_in + f * a.fs_spec + a.nyo + (row0 + r);
         c2<T>* ar = rb + (r * SL + (f == 0 ? 0 : f + 1)) * SC;
         c2<T> v[E];
-        wave_c2r_pre<T, NH, E>(v, src, ar, t, lt);
+        wave_c2r_pre<T, NH, E>(v, src, nyq, ar, t, lt);
         team_fft<T, NH, E, true, 1, true>(v, t, ar, tws);
         team_sync<true>();
 #pragma unroll
@@ -483,6 +546,7 @@ rowpass_kernel(XArgs<T> a) {
       a.partials[2 * blockIdx.x + 0] = acc[0];
       a.partials[2 * blockIdx.x + 1] = acc[1];
     }
+    if (a.sum_count) finish_sums<2>(a.partials, a.sum_count, a.sum_out, a.sum_scale, red);
   }
   __syncthreads();
 
@@ -509,6 +573,7 @@ rowpass_kernel(XArgs<T> a) {
         for (int m = 0; m < E; ++m) ar[pad(t + TEAM * m)] = v[m];
         team_sync<true>();
         c2<T>* dst = a.b_out + o * a.fs_spec + (long long)(row0 + r) * a.Sx;
+        c2<T>* dstn = a.b_out + o * a.fs_spec + a.nyo + (row0 + r);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
           const int k = t + TEAM * m;
@@ -519,7 +584,7 @@ rowpass_kernel(XArgs<T> a) {
           const c2<T> B2 = mk<T>(d.y, -d.x);
           const c2<T> WB = cmul<T>(B2, lt.w[m]);
           dst[k] = mk<T>(T(0.5) * (sm.x + WB.x), T(0.5) * (sm.y + WB.y));
-          if (k == 0) dst[NH] = mk<T>(T(0.5) * (sm.x - B2.x), T(0.5) * (sm.y - B2.y));
+          if (k == 0) *dstn = mk<T>(T(0.5) * (sm.x - B2.x), T(0.5) * (sm.y - B2.y));
         }
       }
     }
@@ -554,6 +619,7 @@ struct AdjArgs {
   const double* mean_c;
   double* partials;
   long long fs_real, fs_spec;
+  long long nyo;  // offset of the Nyquist values within an x-spectrum field
   int rows, Sx, F, do_fwd;
   FeParams<T> fe;
   T dtM, dtL;
@@ -593,11 +659,14 @@ adj_row_kernel(AdjArgs<T> a) {
 
   // w[0] = e_c, w[1..p] = e_i, bc = b_c; w is overwritten by lambda^n
   c2<T> w[FB][E], bc[E];
-  row_c2r<T, NX, E>(w[0], a.s_in + rrow * a.Sx, active, t, my, lt, tws);
-  row_c2r<T, NX, E>(bc, a.s_in + a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
+  row_c2r<T, NX, E>(w[0], a.s_in + rrow * a.Sx, a.s_in + a.nyo + rrow, active, t, my, lt, tws);
+  row_c2r<T, NX, E>(bc, a.s_in + a.fs_spec + rrow * a.Sx, a.s_in + a.fs_spec + a.nyo + rrow, active, t, my,
+                    lt, tws);
 #pragma unroll
   for (int i = 0; i < PMAX; ++i)
-    if (i < p) row_c2r<T, NX, E>(w[1 + i], a.s_in + (2 + i) * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
+    if (i < p)
+      row_c2r<T, NX, E>(w[1 + i], a.s_in + (2 + i) * a.fs_spec + rrow * a.Sx,
+                        a.s_in + (2 + i) * a.fs_spec + a.nyo + rrow, active, t, my, lt, tws);
 
   double q[4] = {0.0, 0.0, 0.0, 0.0};
   const double cmean = *a.mean_c;
@@ -664,7 +733,9 @@ adj_row_kernel(AdjArgs<T> a) {
   if (a.do_fwd) {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
-      if (f < F) row_r2c<T, NX, E>(w[f], a.b_out + f * a.fs_spec + rrow * a.Sx, active, t, my, lt, tws);
+      if (f < F)
+        row_r2c<T, NX, E>(w[f], a.b_out + f * a.fs_spec + rrow * a.Sx, a.b_out + f * a.fs_spec + a.nyo + rrow,
+                          active, t, my, lt, tws);
   }
 }
 
@@ -704,9 +775,10 @@ adjrow_kernel(AdjArgs<T> a) {
       const int sl = j - r * nin;
       if (j < njobs && row0 + r < a.rows) {
         const c2<T>* src = a.s_in + sl * a.fs_spec + (long long)(row0 + r) * a.Sx;
+        const c2<T>* nyq = a.s_in + sl * a.fs_spec + a.nyo + (row0 + r);
         c2<T>* ar = rb + (r * SL + sl) * SC;
         c2<T> v[E];
-        wave_c2r_pre<T, NH, E>(v, src, ar, t, lt);
+        wave_c2r_pre<T, NH, E>(v, src, nyq, ar, t, lt);
         team_fft<T, NH, E, true, 1, true>(v, t, ar, tws);
         team_sync<true>();
 #pragma unroll
@@ -814,6 +886,7 @@ adjrow_kernel(AdjArgs<T> a) {
         for (int m = 0; m < E; ++m) ar[pad(t + TEAM * m)] = v[m];
         team_sync<true>();
         c2<T>* dst = a.b_out + f * a.fs_spec + (long long)(row0 + r) * a.Sx;
+        c2<T>* dstn = a.b_out + f * a.fs_spec + a.nyo + (row0 + r);
 #pragma unroll
         for (int m = 0; m < E; ++m) {
           const int k = t + TEAM * m;
@@ -824,7 +897,7 @@ adjrow_kernel(AdjArgs<T> a) {
           const c2<T> B2 = mk<T>(d.y, -d.x);
           const c2<T> WB = cmul<T>(B2, lt.w[m]);
           dst[k] = mk<T>(T(0.5) * (sm.x + WB.x), T(0.5) * (sm.y + WB.y));
-          if (k == 0) dst[NH] = mk<T>(T(0.5) * (sm.x - B2.x), T(0.5) * (sm.y - B2.y));
+          if (k == 0) *dstn = mk<T>(T(0.5) * (sm.x - B2.x), T(0.5) * (sm.y - B2.y));
         }
       }
     }
@@ -851,8 +924,10 @@ struct ColArgs {
   long long fs_src, fs_dst;  // field strides (complex elements)
   long long ls;              // stride between consecutive transform elements
   long long os;              // stride between outer planes
-  int ncols;                 // active columns (Nx/2 + 1)
-  int nyq;                   // Nx/2 (Hermitian weight 1 at columns 0 and nyq)
+  long long nyo;             // offset of the Nyquist values within a field
+  long long nls, nos;        // Nyquist values: element stride, outer-row stride
+  int ncols;                 // regular columns (Nx/2: kx = 0 .. Nx/2 - 1)
+  int nyq;                   // Nx/2, the Nyquist column (Hermitian weight 1 at columns 0 and nyq)
   int F, mode;
   int first;  // update mode: take c^ from src field 0 (and transform it) instead of cstate
   int f0;     // forward/inverse modes: first field transformed
@@ -889,7 +964,10 @@ __host__ __device__ inline int col_order(int nouter) {
   return nouter > 1 ? PF_COL_ORDER3D : (sizeof(T) == 4 ? 1 : 0);
 }
 
-// One work-group per (column tile, outer index, field group).  Field groups:
+// One work-group per (column tile, outer index, field group), plus, ahead of
+// them, one per (block of C outer indices, field group) for the Nyquist
+// column, whose values sit apart from the tiles (see the layout above); a
+// Nyquist item's C lane columns are C outer rows.  Field groups:
 // forward/inverse: one per field; update and adjoint: the c group (which
 // needs c^ and g^ together) and one per eta_i; energy: one per field.
 // Blocks are dealt to the eight XCDs round-robin (block b runs on XCD b % 8),
@@ -901,16 +979,26 @@ __host__ __device__ inline int col_order(int nouter) {
 template <typename T, int N, int MODE>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, ColGeom<T, N>::WG),
                                amdgpu_waves_per_eu(ColGeom<T, N>::MIN_WAVES)))
-col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
+col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots, int nqb) {
   using G = ColGeom<T, N>;
   constexpr int E = G::E, TEAM = G::TEAM, C = G::C;
-  const int b = blockIdx.x;
   int L, g, tile, o;
   const int order = col_order<T>(nouter);
-  if (order == 2) {
+  // blocks [0, nqb): Nyquist items, C outer rows of the Nyquist column each
+  // (nqb is a multiple of 8, so the XCD of a regular block is unchanged)
+  const int nqi = (nouter + C - 1) / C;  // Nyquist items per field group
+  if (int(blockIdx.x) < nqb) {
+    const int j = blockIdx.x;
+    if (j >= nqi * ngroups) return;
+    g = j / nqi;
+    o = (j - g * nqi) * C;  // first outer row
+    tile = -1;
+    L = tiles * nouter * ngroups + j;
+  } else if (order == 2) {
     // outer row o on XCD o % 8, rows of one XCD in increasing order, field
     // group by group: at any time the XCDs stream through neighbouring rows
     // of each plane (one contiguous region per plane rather than eight)
+    const int b = int(blockIdx.x) - nqb;
     const int nu = tiles * nouter;
     const int rpx = (nouter + 7) / 8;
     const int j = b >> 3;
@@ -926,6 +1014,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
     // chunks of `nslots` units; XCD x takes chunk x for every field group,
     // group by group, so neighbouring tiles of one field run back to back on
     // one L2 and every XCD gets the same mix of c and eta groups.
+    const int b = int(blockIdx.x) - nqb;
     const int nu = tiles * nouter;
     const int j = b >> 3;
     g = j / nslots;
@@ -936,6 +1025,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
     o = u / tiles;
   } else {
     // field group fastest over a contiguous run of work items per XCD
+    const int b = int(blockIdx.x) - nqb;
     L = (b & 7) * nslots + (b >> 3);
     if (L >= tiles * nouter * ngroups) return;
     g = L % ngroups;
@@ -948,8 +1038,11 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   const int lane = threadIdx.x;
   const int cc = lane % C;
   const int t = lane / C;
-  const int col = tile * C + cc;
-  const bool active = col < a.ncols;
+  const bool nyqi = tile < 0;  // work-group uniform
+  // a Nyquist item's lanes cc are C consecutive outer rows of column nyq
+  const int col = nyqi ? a.nyq : tile * C + cc;
+  const int orow = nyqi ? o + cc : o;
+  const bool active = nyqi ? orow < nouter : col < a.ncols;
   c2<T>* my = lds + cc;
   c2<T>* my2 = PF_COL_PINGPONG ? lds + lds_span(N) * C + cc : nullptr;
   int par = 0;  // exchange parity across the transforms of this work-group
@@ -959,12 +1052,14 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
   // offset that is the same for every m, so the address arithmetic runs on
   // the scalar unit.  The offset is below 2^32 for every supported shape
   // (at most C + TEAM ls complex values).
-  const long long wg0 = (long long)o * a.os + (long long)tile * C;
-  const unsigned lbo = (unsigned(cc) + unsigned(t) * unsigned(a.ls)) * unsigned(sizeof(c2<T>));
+  const long long ls = nyqi ? a.nls : a.ls;
+  const long long wg0 = nyqi ? a.nyo + (long long)o * a.nos : (long long)o * a.os + (long long)tile * C;
+  const unsigned lbo = (unsigned(cc) * unsigned(nyqi ? a.nos : 1) + unsigned(t) * unsigned(ls)) *
+                       unsigned(sizeof(c2<T>));
   auto load = [&](const c2<T>* src, c2<T>* v) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const char* pm = reinterpret_cast<const char*>(src + wg0 + (long long)m * TEAM * a.ls);
+      const char* pm = reinterpret_cast<const char*>(src + wg0 + (long long)m * TEAM * ls);
       v[m] = active ? *reinterpret_cast<const c2<T>*>(pm + lbo) : mk<T>(T(0), T(0));
     }
   };
@@ -972,12 +1067,12 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots) {
     if (active) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        char* pm = reinterpret_cast<char*>(dst + wg0 + (long long)m * TEAM * a.ls);
+        char* pm = reinterpret_cast<char*>(dst + wg0 + (long long)m * TEAM * ls);
         *reinterpret_cast<c2<T>*>(pm + lbo) = v[m];
       }
     }
   };
-  const T kc = a.kcol[active ? col : 0] + (a.kouter ? a.kouter[o] : T(0));
+  const T kc = a.kcol[active ? col : 0] + (a.kouter ? a.kouter[active ? orow : 0] : T(0));
   Twiddles<T, N, E> tws;
   tws.load(t, a.tw, 1);
 

@@ -134,8 +134,7 @@ pf_status pf_step_fs(pf_handle* h, double dt, int64_t nsteps);
  * nothing: no hipMalloc, hipFree or allocating library call.  Runs on the
  * current device; the first call on a device looks up the array's device
  * address.  The tables are re-uploaded (hipMemcpyAsync from host memory
- * the handle holds) and the one counter the step needs at zero is cleared
- * (by a one-thread kernel) on every call; every other workspace value the step
+ * the handle holds) on every call, and every workspace value the step
  * reads is written earlier in the same call, so nothing carries over
  * between calls.  All calls on one GPU share the one array: calls that overlap in
  * time on one GPU (other streams, other threads) race and give wrong

@@ -29,15 +29,4 @@ int reduce_launch(const double* partials, int n, int width, double* out, const d
   return 1;
 }
 
-// Clears the arrival counter of the in-kernel sum finish (a kernel rather
-// than hipMemsetAsync, so the call sequence holds no memset node when a
-// caller captures it in a graph).
-__global__ void __launch_bounds__(64) clear_kernel(unsigned* p) {
-  if (threadIdx.x == 0) *p = 0u;
-}
-
-void clear_launch(unsigned* p, hipStream_t s) {
-  hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(64), 0, s, p);
-}
-
 }  // namespace pf

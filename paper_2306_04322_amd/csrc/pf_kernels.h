@@ -111,48 +111,7 @@ struct XArgs {
   int rows, Sx, F, flags;
   FeParams<T> fe;
   T dtL;
-  // optional in-kernel finish of the double sums (X_ESUM / X_CSUM): when
-  // sum_count is set, the last work-group to finish adds up every group's
-  // record in a fixed order and writes sum_out[i] = sum_scale[i] * total[i]
-  unsigned* sum_count;
-  double* sum_out;
-  double sum_scale[2];
 };
-
-// Fixed-order finish of per-work-group double records: called by every
-// thread of every work-group after thread 0 has written the group's record
-// partials[blockIdx.x * NV + i].  The last group to arrive (counted on
-// *count, which must be 0 at launch and is reset to 0 here) sums all
-// gridDim.x records, each thread a fixed strided subset, then the fixed
-// work-group reduction, so the result does not depend on which group is
-// last or on timing.
-template <int NV>
-__device__ __forceinline__ void finish_sums(const double* partials, unsigned* count, double* out,
-                                            const double* scale, double* red) {
-  __shared__ int is_last;
-  if (threadIdx.x == 0) {
-    __threadfence();  // this group's record before the count
-    const unsigned prev = atomicAdd(count, 1u);
-    is_last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (is_last) {  // uniform across the work-group
-    __threadfence();  // every group's record after the count
-    double acc[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (unsigned r = threadIdx.x; r < gridDim.x; r += blockDim.x) {
-#pragma unroll
-      for (int i = 0; i < NV; ++i) acc[i] += partials[(long long)r * NV + i];
-    }
-    block_sum<NV>(acc, red);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int i = 0; i < NV; ++i) out[i] = acc[i] * scale[i];
-      *count = 0u;
-    }
-  }
-}
 
 // Row pass geometry for a real length NX.
 template <typename T, int NX, int PMAX>
@@ -296,7 +255,6 @@ xpass_kernel(XArgs<T> a) {
       a.partials[2 * blockIdx.x + 0] = acc[0];
       a.partials[2 * blockIdx.x + 1] = acc[1];
     }
-    if (a.sum_count) finish_sums<2>(a.partials, a.sum_count, a.sum_out, a.sum_scale, red);
   }
 
   if (a.flags & X_FWD_DERIV) {
@@ -546,7 +504,6 @@ rowpass_kernel(XArgs<T> a) {
       a.partials[2 * blockIdx.x + 0] = acc[0];
       a.partials[2 * blockIdx.x + 1] = acc[1];
     }
-    if (a.sum_count) finish_sums<2>(a.partials, a.sum_count, a.sum_out, a.sum_scale, red);
   }
   __syncthreads();
 
@@ -918,7 +875,7 @@ struct ColArgs {
   const T* kcol;       // |xi|^2 table indexed by the column (x frequency)
   const T* kaxis;      // |xi|^2 table of the transformed axis
   const T* kouter;     // |xi|^2 table indexed by the outer index (3D z pass), or null
-  const double* mean_c;  // double mean of c (held k = 0 mode)
+  double* mean_c;        // double mean of c (held k = 0 mode); written by the first update
   c2<T>* cstate;         // carried spectrum of c (update mode), x-spectrum layout
   double* partials;
   long long fs_src, fs_dst;  // field strides (complex elements)
@@ -930,8 +887,10 @@ struct ColArgs {
   int nyq;                   // Nx/2, the Nyquist column (Hermitian weight 1 at columns 0 and nyq)
   int F, mode;
   int first;  // update mode: take c^ from src field 0 (and transform it) instead of cstate
+  int nrec;   // first update: row-pass records {sum f, sum c} in partials to take the mean of c from
   int f0;     // forward/inverse modes: first field transformed
   T dtM, dtMkc, dtL, dtLke, invP;
+  double invPd;  // 1 / P in double
 };
 
 // Column-pass geometry.  E = 8 elements per lane (N / 8 lanes per column),
@@ -1096,6 +1055,25 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots, int nqb
       }
       par = team_fft<T, N, E, false, C>(gg, t, my, tws, my2, par);
       if constexpr (MODE == COL_UPDATE_FIRST) par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
+      // the held k = 0 mode: P times the double-precision mean of c.  On the
+      // first step of a call the work item that holds it (tile 0, outer row
+      // 0) adds up the row pass's per-group sums of c in a fixed order and
+      // keeps the mean for the later steps; the row pass has completed (a
+      // kernel boundary), so no fence is needed.
+      double cmean = 0.0;
+      if constexpr (MODE == COL_UPDATE_FIRST) {
+        if (tile == 0 && o == 0) {  // work-group uniform
+          double acc[1] = {0.0};
+          for (int r = threadIdx.x; r < a.nrec; r += blockDim.x) acc[0] += a.partials[2 * (long long)r + 1];
+          block_sum<1>(acc, red);
+          if (threadIdx.x == 0) {
+            cmean = acc[0] * a.invPd;
+            *a.mean_c = cmean;
+          }
+        }
+      } else {
+        if (col == 0 && o == 0 && t == 0) cmean = *a.mean_c;
+      }
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const T k2 = kc + a.kaxis[t + TEAM * m];
@@ -1108,7 +1086,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots, int nqb
       for (int m = 0; m < E; ++m) {
         const int e = t + TEAM * m;
         v[m] = mk<T>(v[m].x * a.invP, v[m].y * a.invP);
-        if (col == 0 && o == 0 && e == 0) v[m] = mk<T>(T(*a.mean_c), T(0));
+        if (col == 0 && o == 0 && e == 0) v[m] = mk<T>(T(cmean), T(0));
       }
       par = team_fft<T, N, E, true, C>(v, t, my, tws, my2, par);
       store(a.dst, v);

@@ -21,6 +21,5 @@ template <typename T> int col_launch(int n, int nouter, const ColArgs<T>& a, hip
 template <typename T> int fd_launch(int which, int p, const FdArgs<T>& a, hipStream_t s);
 int reduce_launch(const double* partials, int n, int width, double* out, const double* scale4,
                   int accumulate, hipStream_t s);
-void clear_launch(unsigned* p, hipStream_t s);
 
 }  // namespace pf

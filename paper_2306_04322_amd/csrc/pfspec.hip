@@ -181,10 +181,7 @@ double* partials(const pf_handle* h) { return reinterpret_cast<double*>(h->ws + 
 double* scal(const pf_handle* h) { return reinterpret_cast<double*>(h->ws + h->off_scal); }
 
 // scalar slots in the workspace
-enum { SC_FSUM = 0, SC_MEANC = 1, SC_EN = 4, SC_DPAR = 12, SC_COUNT = 60 };
-// arrival counter of the in-kernel sum finish (an unsigned in a double slot;
-// zero between kernels)
-unsigned* sum_counter(const pf_handle* h) { return reinterpret_cast<unsigned*>(scal(h) + SC_COUNT); }
+enum { SC_MEANC = 1, SC_EN = 4, SC_DPAR = 12 };
 
 template <typename T>
 XArgs<T> xargs(const pf_handle* h) {
@@ -230,6 +227,7 @@ ColArgs<T> cargs(const pf_handle* h, double dt) {
   a.dtL = T(dt * h->L);
   a.dtLke = T(dt * h->L * h->ke);
   a.invP = T(1.0 / double(h->P));
+  a.invPd = 1.0 / double(h->P);
   return a;
 }
 
@@ -288,9 +286,10 @@ pf_status reduce(pf_handle* h, int n, int width, double* out, double s0, double 
 // carried state; later steps reuse the carried state and B holds only the
 // F right-hand sides in fields 1..F.
 template <typename T>
-pf_status spectral_update(pf_handle* h, double dt, bool first) {
+pf_status spectral_update(pf_handle* h, double dt, bool first, int nrec) {
   ColArgs<T> a = cargs<T>(h, dt);
   a.first = first ? 1 : 0;
+  a.nrec = nrec;
   if (h->nd == 2) {
     a.src = specB<T>(h);
     a.dst = specS<T>(h);
@@ -330,16 +329,13 @@ pf_status fs_run(pf_handle* h, double dt, long long nsteps, const T* uin, T* uou
   x.u_in = uin;
   x.b_out = specB<T>(h);
   x.flags = X_LOAD_REAL | X_FWD_DERIV | X_WITH_C | X_CSUM;
-  // the mean of c (the held k = 0 mode) is finished by the row pass's last
-  // work-group
-  x.sum_count = sum_counter(h);
-  x.sum_out = scal(h) + SC_FSUM;
-  x.sum_scale[0] = 1.0;
-  x.sum_scale[1] = 1.0 / double(h->P);
-  PF_TRY(row<T>(h, x, nullptr));
+  // the row pass writes one record {0, sum c} per work-group; the first
+  // update pass takes the mean of c (the held k = 0 mode) from them
+  int nb = 0;
+  PF_TRY(row<T>(h, x, &nb));
   const long long fsz = (long long)h->F * h->P;
   for (long long s = 0; s < nsteps; ++s) {
-    PF_TRY(spectral_update<T>(h, dt, s == 0));
+    PF_TRY(spectral_update<T>(h, dt, s == 0, nb));
     XArgs<T> y = xargs<T>(h);
     y.dtL = T(dt * h->L);
     y.s_in = specS<T>(h);
@@ -741,7 +737,6 @@ pf_status pf_bind(pf_handle* h, void* fields, void* workspace, size_t workspace_
   h->ws = static_cast<char*>(workspace);
   if (hipMemcpyAsync(h->ws + h->off_tw[0], h->staging.data(), h->staging.size(),
                      hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-      (clear_launch(sum_counter(h), h->stream), hipGetLastError()) != hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess)
     return fail(PF_ERR_HIP, std::string("table upload: ") + hipGetErrorString(hipGetLastError()));
   return PF_OK;
@@ -801,10 +796,6 @@ pf_status pf_step_fs_static(pf_handle* h, void* fields, double dt, int64_t nstep
   if (hipMemcpyAsync(ws + h->off_tw[0], h->staging.data(), h->staging.size(), hipMemcpyHostToDevice,
                      h->stream) != hipSuccess)
     return fail(PF_ERR_HIP, std::string("table upload: ") + hipGetErrorString(hipGetLastError()));
-  // the arrival counter of the sum finish must be zero: an earlier call with
-  // another configuration may have left other data at its place
-  clear_launch(reinterpret_cast<unsigned*>(ws + h->off_scal + SC_COUNT * sizeof(double)), h->stream);
-  PF_TRY(check_launch("counter clear"));
   // run on the scratch, then restore the handle's own binding (if any)
   char* const ws_bound = h->ws;
   void* const fields_bound = h->fields;

@@ -254,10 +254,11 @@ def main(argv=None):
     s32.set_fields(u0)
     # each steady-state pass timed on its own, back to back between two HIP
     # events on the library's stream (pf_time_pass); the passes read and
-    # write the workspace only, after two steps have filled it.  Run before
-    # the headline, so that the headline, like every later measurement,
-    # starts on a GPU that has been busy rather than idle.
-    s32.step_fs(dt, 2)
+    # write the workspace only, after untimed steps have filled it (and
+    # brought the GPU out of idle).  Run before the headline, so that the
+    # headline, like every later measurement, starts on a GPU that has been
+    # busy rather than idle.
+    s32.step_fs(dt, 100)
     reps = max(50, min(args.steps, 500))
     rates = pass_rates(s32, cfg, "f32", reps)
 
@@ -286,7 +287,8 @@ def main(argv=None):
             "other_kernel": dict(name=oth, **rates[oth]),
             "cache": "the 1024^2 FP32 working set (about 80 MB) fits the 256 MB last-level "
                      "cache, so these rates are partly served from that cache; "
-                     "extras.fs_2d_4096_f32 is an HBM-resident 2D case"}
+                     "extras.fs_2d_2048_* and fs_2d_4096_* are 2D cases whose working sets "
+                     "(about 0.3 and 1.2 GB in FP32) exceed it"}
     cbw = copy_bandwidth(torch, dev)
     roof["copy_GBs"] = round(cbw, 1)
     roof["frac_of_copy"] = round(rd["achieved_GBs"] / cbw, 4)
@@ -361,25 +363,27 @@ def main(argv=None):
         log("fp64 %.3f ms/step; fp32/fp64 = %.2f" % (1e3 * t64 / n64, value / v64))
         del s64
         torch.cuda.empty_cache()
-        # an HBM-resident 2D case: 4096^2, F = 5 (working set about 1.2 GB
-        # in FP32, above the 256 MB last-level cache)
-        cfgL = I.make_config(2, 4096, 1.0, 4, I.PAPER_FE)
-        uL = I.random_ic(cfgL, seed=0).astype(np.float32).astype(np.float64)
-        PL = 4096 * 4096
-        for prec, nL in (("f32", 100), ("f64", 50)):
-            sL = Solver(cfgL, prec)
-            sL.set_fields(uL)
-            tL = time_fs(sL, dt, nL, 10, torch)
-            rec = {"value": PL * nL / tL, "ms_per_step": 1e3 * tL / nL,
-                   "step_frac_9Fs": round(PL * nL / tL * 9 * 5 * (4 if prec == "f32" else 8)
-                                          / (HBM_PEAK_GBS * 1e9), 4),
-                   "passes": pass_rates(sL, cfgL, prec, 50)}
-            extras["fs_2d_4096_" + prec] = rec
-            log("2D 4096^2 %s %.3f ms/step" % (prec, rec["ms_per_step"]))
-            del sL
-            torch.cuda.empty_cache()
-        extras["fs_2d_4096_f32_over_f64"] = (extras["fs_2d_4096_f32"]["value"]
-                                             / extras["fs_2d_4096_f64"]["value"])
+        # 2D cases whose working sets exceed the 256 MB last-level cache:
+        # 2048^2 (about 0.3 GB in FP32; the same row and column kernel forms
+        # as 1024^2) and 4096^2 (about 1.2 GB; long-row forms)
+        for nL, steps in ((2048, (200, 100)), (4096, (100, 50))):
+            cfgL = I.make_config(2, nL, 1.0, 4, I.PAPER_FE)
+            uL = I.random_ic(cfgL, seed=0).astype(np.float32).astype(np.float64)
+            PL = nL * nL
+            for prec, nS in zip(("f32", "f64"), steps):
+                sL = Solver(cfgL, prec)
+                sL.set_fields(uL)
+                tL = time_fs(sL, dt, nS, 10, torch)
+                rec = {"value": PL * nS / tL, "ms_per_step": 1e3 * tL / nS,
+                       "step_frac_9Fs": round(PL * nS / tL * 9 * 5 * (4 if prec == "f32" else 8)
+                                              / (HBM_PEAK_GBS * 1e9), 4),
+                       "passes": pass_rates(sL, cfgL, prec, 50)}
+                extras["fs_2d_%d_%s" % (nL, prec)] = rec
+                log("2D %d^2 %s %.3f ms/step" % (nL, prec, rec["ms_per_step"]))
+                del sL
+                torch.cuda.empty_cache()
+            extras["fs_2d_%d_f32_over_f64" % nL] = (extras["fs_2d_%d_f32" % nL]["value"]
+                                                    / extras["fs_2d_%d_f64" % nL]["value"])
         # explicit FD on the same grid and state (stable dt of the FD scheme)
         sfd = Solver(cfg, "f32")
         sfd.set_fields(u0)

@@ -913,18 +913,14 @@ struct ColGeom {
 
 // Work order of the column pass (see col_kernel), the faster choice for
 // each case on MI355X: 0 = field group fastest over a contiguous run of
-// items per XCD (2D), 1 = per-XCD chunks of tiles (kept as an alternative
-// for 2D float), 2 = outer rows dealt to the XCDs round-robin (3D passes).
+// items per XCD (2D double), 1 = per-XCD chunks of tiles (2D float),
+// 2 = outer rows dealt to the XCDs round-robin (3D passes).
 #ifndef PF_COL_ORDER3D
 #define PF_COL_ORDER3D 2
 #endif
-#ifndef PF_COL_ORDER2D_F32
-#define PF_COL_ORDER2D_F32 0  // 2D float: field group fastest, as for double (measured
-                              // 31.6 against 31.8 us per 1024^2 step with per-XCD chunks)
-#endif
 template <typename T>
 __host__ __device__ inline int col_order(int nouter) {
-  return nouter > 1 ? PF_COL_ORDER3D : (sizeof(T) == 4 ? PF_COL_ORDER2D_F32 : 0);
+  return nouter > 1 ? PF_COL_ORDER3D : (sizeof(T) == 4 ? 1 : 0);
 }
 
 // One work-group per (column tile, outer index, field group), plus, ahead of

@@ -16,11 +16,15 @@ caught.  Trajectories (Algorithm 1; Eq. (12)-(15), (19)):
   w2     2D 1024^2, c + 4 eta, seeded uniform state, dt = 0.1, 200 steps
   paper  2D 1024^2, c + 4 eta, Eq. (4)-(5) state at dx = 1, dt = 0.01, 200 steps
   w3     3D 256^3,  c + 4 eta, seeded uniform state, dt = 0.1, 2 steps
+  w5     3D 128^3,  c + 4 eta, seeded uniform state, dt = 0.1, 3 steps, then
+         the discrete adjoint of those steps from a seeded terminal
+         cotangent; stored are dJ/du^0 on sampled lines (with its per-field
+         sums) and the four parameter gradients
 
 Every run starts from the FP32-rounded initial state, so one trajectory
 serves the FP32 and the FP64 GPU paths.
 
-Usage (from the repository root; about 15 minutes on 8 host cores):
+Usage (from the repository root; about 17 minutes on 8 host cores):
     python tests/golden/make_fullsize_golden.py [w2 paper w3]
 """
 
@@ -36,6 +40,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from oracle import adjoint as oadj  # noqa: E402
 from oracle import fs as ofs  # noqa: E402
 from paper_2306_04322_amd import inputs as I  # noqa: E402
 
@@ -45,6 +50,10 @@ WORKERS = 5
 ROWS_2D = (0, 1, 517, 1023)
 LINES_3D = ((0, 0), (0, 255), (1, 128), (77, 3), (128, 128), (200, 31),
             (254, 200), (255, 255))
+# (z, y) lines of the 128^3 adjoint grid
+LINES_W5 = ((0, 0), (0, 127), (1, 64), (45, 3), (64, 64), (100, 31), (127, 127))
+# seed of the terminal cotangent dJ/du^T of the adjoint case
+W5_LAMBDA_SEED = 21
 
 
 def source_digest():
@@ -75,21 +84,49 @@ def trajectory(name):
     if name == "w3":
         cfg, w = I.workload_config("W3")
         return cfg, w["dt_fs"], 2, fp32_rounded(I.workload_ic(cfg, w))
+    if name == "w5":
+        cfg, w = I.workload_config("W5")
+        return cfg, w["dt_fs"], 3, fp32_rounded(I.workload_ic(cfg, w))
     raise KeyError(name)
+
+
+def w5_lambda_T(cfg):
+    """The seeded terminal cotangent of the adjoint case (FP32-rounded, so
+    the FP32 GPU path starts from the same values)."""
+    return fp32_rounded(I.random_direction(cfg, W5_LAMBDA_SEED))
 
 
 def sample(u, ndim):
     """The stored lines of the fields u (F, ...): (F, lines, Nx)."""
     if ndim == 2:
         return np.ascontiguousarray(u[:, list(ROWS_2D), :])
-    return np.ascontiguousarray(np.stack([u[:, z, y, :] for z, y in LINES_3D], axis=1))
+    lines = LINES_3D if u.shape[-1] == 256 else LINES_W5
+    return np.ascontiguousarray(np.stack([u[:, z, y, :] for z, y in lines], axis=1))
 
 
 def path_of(name):
     return os.path.join(HERE, "fullsize_%s.npz" % name)
 
 
+def write_adjoint(name):
+    cfg, dt, steps, u0 = trajectory(name)
+    t0 = time.time()
+    traj = oadj.trajectory(u0, cfg, dt, steps)
+    lam0, dpar = oadj.fs_adjoint(traj, w5_lambda_T(cfg), cfg, dt)
+    flat = lam0.reshape(lam0.shape[0], -1)
+    np.savez(path_of(name),
+             digest=np.array(source_digest()),
+             dt=np.array(dt), steps=np.array(steps),
+             sample=sample(lam0, cfg["ndim"]),
+             field_sum=flat.sum(axis=1), field_sumsq=(flat ** 2).sum(axis=1),
+             dpar=dpar)
+    print("%s: %d oracle steps and their adjoint in %.0f s -> %s"
+          % (name, steps, time.time() - t0, path_of(name)), flush=True)
+
+
 def write(name):
+    if name == "w5":
+        return write_adjoint(name)
     cfg, dt, steps, u0 = trajectory(name)
     t0 = time.time()
     ref = ofs.fs_run(u0, cfg, dt, steps, workers=WORKERS)
@@ -104,5 +141,5 @@ def write(name):
 
 
 if __name__ == "__main__":
-    for nm in (sys.argv[1:] or ["w2", "paper", "w3"]):
+    for nm in (sys.argv[1:] or ["w2", "paper", "w3", "w5"]):
         write(nm)

@@ -42,3 +42,17 @@ def test_sample_lines_cover_both_axis_ends():
     zs = [z for z, _ in G.LINES_3D]
     ys = [y for _, y in G.LINES_3D]
     assert min(zs) == 0 and max(zs) == 255 and min(ys) == 0 and max(ys) == 255
+
+
+def test_stored_adjoint_values_current():
+    z = np.load(G.path_of("w5"))
+    assert str(z["digest"]) == G.source_digest(), "rerun make_fullsize_golden.py w5"
+    cfg, dt, steps, u0 = G.trajectory("w5")
+    assert float(z["dt"]) == dt and int(z["steps"]) == steps
+    assert cfg["n"] == (128, 128, 128) and cfg["p"] == 4
+    assert z["sample"].shape == (5, len(G.LINES_W5), 128)
+    assert np.all(np.isfinite(z["sample"])) and np.all(np.isfinite(z["dpar"]))
+    assert z["dpar"].shape == (4,) and np.all(z["dpar"] != 0)
+    zs = [zz for zz, _ in G.LINES_W5]
+    ys = [y for _, y in G.LINES_W5]
+    assert min(zs) == 0 and max(zs) == 127 and min(ys) == 0 and max(ys) == 127

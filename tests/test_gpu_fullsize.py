@@ -18,7 +18,12 @@ Fields whose reference norm falls below the floor of `parity_util.rel_l2`
 are reported and not compared: on the seeded uniform initial state of the
 throughput workload the order parameters vanish within a few steps at
 dt = 0.1 (dt L d2f/deta2 = 1 at eta = 0), in the oracle and on the GPU alike.
-The 1024^2 run of the Eq. (4)-(5) state keeps all five fields non-trivial."""
+The 1024^2 run of the Eq. (4)-(5) state keeps all five fields non-trivial.
+
+The discrete adjoint is checked at the differentiable 3D shape (128^3,
+c + 4 eta) over three steps in two checkpoint segments (2 + 1 steps): the
+gradient with respect to the initial fields on the sampled lines and as
+whole-field aggregates, and the four parameter gradients."""
 
 import os
 import sys
@@ -107,3 +112,48 @@ def test_w3_256_random_ic(prec):
     assert all(e is not None for e in errs)
     assert max_rel(errs) <= TOL[prec]
     assert max(e for e in rms_err) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_w5_adjoint_128(prec):
+    """Differentiable 3D workload, 128^3, c + 4 eta, dt = 0.1: the adjoint of
+    three FS steps (checkpoints every 2 steps) from a seeded cotangent."""
+    torch = gpu_or_fail()
+    from paper_2306_04322_amd.pfspec import Solver
+    z = _golden("w5")
+    cfg, dt, steps, u0 = G.trajectory("w5")
+    K = 2
+    announce("adjoint full w5", cfg["n"], "steps", steps, "K", K, prec)
+    s = Solver(cfg, prec)
+    s.set_fields(u0)
+    ckpts, lens, done = [], [], 0
+    while done < steps:
+        k = min(K, steps - done)
+        ckpts.append(s.fields.clone())
+        lens.append(k)
+        s.step_fs(dt, k)
+        done += k
+    lam = torch.as_tensor(G.w5_lambda_T(cfg)).to(s.device, s.dtype).contiguous()
+    seg = s.segment_store(K)
+    dpar = np.zeros(4)
+    for ck, k in zip(reversed(ckpts), reversed(lens)):
+        dpar = s.adjoint_fs(dt, k, ck, lam, seg, dpar)
+    torch.cuda.synchronize()
+    got = lam.double().cpu().numpy()
+    del s, seg, ckpts, lam
+    F = got.shape[0]
+    errs = rel_l2(G.sample(got, 3), z["sample"])
+    flat = got.reshape(F, -1)
+    sum_err = [abs(flat[f].sum() - z["field_sum"][f]) / np.sqrt(z["field_sumsq"][f])
+               for f in range(F)]
+    rms_err = [abs(np.sqrt((flat[f] ** 2).sum()) - np.sqrt(z["field_sumsq"][f]))
+               / np.sqrt(z["field_sumsq"][f]) for f in range(F)]
+    rp = z["dpar"]
+    perr = np.max(np.abs(dpar - rp) / np.abs(rp))
+    print("w5 adjoint %s sampled rel-L2 per field %s; sum err %s; norm err %s; "
+          "params %s oracle %s (max rel %.3e)" % (prec, errs, sum_err, rms_err, dpar, rp, perr))
+    assert all(e is not None for e in errs)
+    assert max_rel(errs) <= TOL[prec]
+    assert max(rms_err) <= TOL[prec]
+    assert max(sum_err) <= TOL[prec]
+    assert perr <= (1e-9 if prec == "f64" else 1e-3)

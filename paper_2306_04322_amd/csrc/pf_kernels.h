@@ -72,6 +72,9 @@
 #ifndef PF_COL_WG_MAX_LONG
 #define PF_COL_WG_MAX_LONG 1024  // largest column work-group, float, length 4096 (2-column tiles)
 #endif
+#ifndef PF_XROW_MIN_WAVES
+#define PF_XROW_MIN_WAVES 2  // register budget, register-form row pass (waves per SIMD)
+#endif
 #ifndef PF_COL_E_LONG_F32
 #define PF_COL_E_LONG_F32 8  // elements per lane, float column transforms of length >= 512
 #endif
@@ -123,32 +126,44 @@ struct XGeom {
   static constexpr int ROWS = TEAM >= 64 ? 1 : 64 / TEAM;
   static constexpr int WG = ROWS * TEAM;
   static constexpr int REGION = lds_span(NH) + 1;  // LDS complex values per team
+  // register budget of the fixed-flag instantiations: two work-groups per
+  // SIMD where a work-group has at most one wavefront per SIMD (with up to
+  // five fields; eight order parameters would spill)
+  static constexpr int MIN_WAVES = (WG <= 256 && PMAX <= 4) ? PF_XROW_MIN_WAVES : 1;
 };
 
-// C2R of one row: x-spectrum src[0..NH-1] and its Nyquist value *nyq ->
-// v[m] = (x[2k], x[2k+1]),
-// k = t + TEAM m, with x the unnormalised inverse over the Hermitian
-// extension (x_j = sum_k X_k exp(+2 pi i j k / NX)).
+// Loads of one x-spectrum row for row_c2r: v[m] = X_k, k = t + TEAM m, and
+// xn = X_NH (lane t = 0; zero elsewhere and for inactive rows).  Issued for
+// all fields of a row before the first transform, so their latencies
+// overlap.
 template <typename T, int NX, int E>
-__device__ __forceinline__ void row_c2r(c2<T>* v, const c2<T>* __restrict__ src,
-                                        const c2<T>* __restrict__ nyq, bool active,
-                                        int t, c2<T>* my, const LaneTwiddles<T, NX / 2, E>& lt,
+__device__ __forceinline__ void row_load(c2<T>* v, c2<T>& xn, const c2<T>* __restrict__ src,
+                                         const c2<T>* __restrict__ nyq, bool active, int t) {
+  constexpr int TEAM = NX / 2 / E;
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = active ? src[t + TEAM * m] : mk<T>(T(0), T(0));
+  xn = (active && t == 0) ? *nyq : mk<T>(T(0), T(0));
+}
+
+// C2R of one row loaded by row_load (v[m] = X_k, xn = X_NH) -> v[m] =
+// (x[2k], x[2k+1]), k = t + TEAM m, with x the unnormalised inverse over the
+// Hermitian extension (x_j = sum_k X_k exp(+2 pi i j k / NX)).
+template <typename T, int NX, int E>
+__device__ __forceinline__ void row_c2r(c2<T>* v, c2<T> xn, int t, c2<T>* my,
+                                        const LaneTwiddles<T, NX / 2, E>& lt,
                                         const Twiddles<T, NX / 2, E>& tws) {
   constexpr int NH = NX / 2;
   constexpr int TEAM = NH / E;
-  c2<T> X[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) X[m] = active ? src[t + TEAM * m] : mk<T>(T(0), T(0));
-#pragma unroll
-  for (int m = 0; m < E; ++m) my[t + TEAM * m] = X[m];
-  if (t == 0) my[NH] = active ? *nyq : mk<T>(T(0), T(0));
+  for (int m = 0; m < E; ++m) my[t + TEAM * m] = v[m];
+  if (t == 0) my[NH] = xn;
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + TEAM * m;
     const c2<T> Y = conj<T>(my[NH - k]);
-    const c2<T> s = add<T>(X[m], Y);
-    const c2<T> d = cmulc<T>(sub<T>(X[m], Y), lt.w[m]);  // * exp(+2 pi i k / NX)
+    const c2<T> s = add<T>(v[m], Y);
+    const c2<T> d = cmulc<T>(sub<T>(v[m], Y), lt.w[m]);  // * exp(+2 pi i k / NX)
     v[m] = mk<T>(s.x - d.y, s.y + d.x);                 // s + i d
   }
   __syncthreads();
@@ -183,8 +198,11 @@ __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* __restrict__ dst, c2<T>
   __syncthreads();
 }
 
-template <typename T, int NX, int PMAX>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, XGeom<T, NX, PMAX>::WG)))
+// FX >= 0 fixes the flags apart from X_STORE_REAL, and FEK >= 0 the
+// free-energy kind with p = PMAX, as in rowpass_kernel below.
+template <typename T, int NX, int PMAX, int FX = -1, int FEK = -1>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, XGeom<T, NX, PMAX>::WG),
+                               amdgpu_waves_per_eu(FX >= 0 ? XGeom<T, NX, PMAX>::MIN_WAVES : 1)))
 xpass_kernel(XArgs<T> a) {
   using G = XGeom<T, NX, PMAX>;
   constexpr int NH = G::NH, E = G::E, TEAM = G::TEAM, ROWS = G::ROWS;
@@ -198,15 +216,16 @@ xpass_kernel(XArgs<T> a) {
   const bool active = row < a.rows;
   const long long rrow = active ? row : 0;
   c2<T>* my = lds + team * G::REGION;
-  const int F = a.F;
+  const int F = FEK >= 0 ? PMAX + 1 : a.F;
   const int p = F - 1;
+  const int flags = FX >= 0 ? (FX | (a.flags & X_STORE_REAL)) : a.flags;
   Twiddles<T, NH, E> tws;
   tws.load(t, a.twx, 2);
   LaneTwiddles<T, NH, E> lt;  // exp(-2 pi i k / NX), k = t + TEAM m
   lt.load(t, a.twx);
 
   c2<T> u[FB][E];
-  if (a.flags & X_LOAD_REAL) {
+  if (flags & X_LOAD_REAL) {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
       if (f < F) {
@@ -215,14 +234,18 @@ xpass_kernel(XArgs<T> a) {
         for (int m = 0; m < E; ++m) u[f][m] = active ? src[t + TEAM * m] : mk<T>(T(0), T(0));
       }
   } else {
+    c2<T> xn[FB];
 #pragma unroll
     for (int f = 0; f < FB; ++f)
       if (f < F)
-        row_c2r<T, NX, E>(u[f], a.s_in + f * a.fs_spec + rrow * a.Sx, a.s_in + f * a.fs_spec + a.nyo + rrow,
-                          active, t, my, lt, tws);
+        row_load<T, NX, E>(u[f], xn[f], a.s_in + f * a.fs_spec + rrow * a.Sx,
+                           a.s_in + f * a.fs_spec + a.nyo + rrow, active, t);
+#pragma unroll
+    for (int f = 0; f < FB; ++f)
+      if (f < F) row_c2r<T, NX, E>(u[f], xn[f], t, my, lt, tws);
   }
 
-  if ((a.flags & X_STORE_REAL) && active) {
+  if ((flags & X_STORE_REAL) && active) {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
       if (f < F) {
@@ -232,7 +255,7 @@ xpass_kernel(XArgs<T> a) {
       }
   }
 
-  if (a.flags & (X_ESUM | X_CSUM)) {
+  if (flags & (X_ESUM | X_CSUM)) {
     double acc[2] = {0.0, 0.0};
     if (active) {
 #pragma unroll
@@ -240,7 +263,7 @@ xpass_kernel(XArgs<T> a) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const T c = h ? u[0][m].y : u[0][m].x;
-          if (a.flags & X_ESUM) {
+          if (flags & X_ESUM) {
             T eta[PMAX];
 #pragma unroll
             for (int i = 0; i < PMAX; ++i) eta[i] = (i < p) ? (h ? u[1 + i][m].y : u[1 + i][m].x) : T(0);
@@ -257,7 +280,7 @@ xpass_kernel(XArgs<T> a) {
     }
   }
 
-  if (a.flags & X_FWD_DERIV) {
+  if (flags & X_FWD_DERIV) {
     // outputs: 0 -> c (X_WITH_C only), 1 -> df/dc, 2 + i -> eta_i - dt L df/deta_i
     c2<T> gcv[E];
 #pragma unroll
@@ -273,7 +296,7 @@ xpass_kernel(XArgs<T> a) {
         }
         const T c = h ? u[0][m].y : u[0][m].x;
         T gc;
-        fe_grad<T, PMAX>(a.fe, p, c, eta, gc, ge);
+        fe_grad<T, PMAX, FEK, (FEK >= 0 ? PMAX : 0)>(a.fe, p, c, eta, gc, ge);
         if (h) gcy = gc; else gcx = gc;
 #pragma unroll
         for (int i = 0; i < PMAX; ++i)
@@ -284,7 +307,7 @@ xpass_kernel(XArgs<T> a) {
       }
       gcv[m] = mk<T>(gcx, gcy);
     }
-    if (a.flags & X_WITH_C)
+    if (flags & X_WITH_C)
       row_r2c<T, NX, E>(u[0], a.b_out + rrow * a.Sx, a.b_out + a.nyo + rrow, active, t, my, lt, tws);
     row_r2c<T, NX, E>(gcv, a.b_out + 1 * a.fs_spec + rrow * a.Sx, a.b_out + 1 * a.fs_spec + a.nyo + rrow,
                       active, t, my, lt, tws);
@@ -293,7 +316,7 @@ xpass_kernel(XArgs<T> a) {
       if (i < p)
         row_r2c<T, NX, E>(u[1 + i], a.b_out + (2 + i) * a.fs_spec + rrow * a.Sx,
                           a.b_out + (2 + i) * a.fs_spec + a.nyo + rrow, active, t, my, lt, tws);
-  } else if (a.flags & X_FWD_RAW) {
+  } else if (flags & X_FWD_RAW) {
 #pragma unroll
     for (int f = 0; f < FB; ++f)
       if (f < F)
@@ -615,15 +638,20 @@ adj_row_kernel(AdjArgs<T> a) {
   lt.load(t, a.twx);
 
   // w[0] = e_c, w[1..p] = e_i, bc = b_c; w is overwritten by lambda^n
-  c2<T> w[FB][E], bc[E];
-  row_c2r<T, NX, E>(w[0], a.s_in + rrow * a.Sx, a.s_in + a.nyo + rrow, active, t, my, lt, tws);
-  row_c2r<T, NX, E>(bc, a.s_in + a.fs_spec + rrow * a.Sx, a.s_in + a.fs_spec + a.nyo + rrow, active, t, my,
-                    lt, tws);
+  c2<T> w[FB][E], bc[E], xn[FB + 1];
+  row_load<T, NX, E>(w[0], xn[0], a.s_in + rrow * a.Sx, a.s_in + a.nyo + rrow, active, t);
+  row_load<T, NX, E>(bc, xn[FB], a.s_in + a.fs_spec + rrow * a.Sx, a.s_in + a.fs_spec + a.nyo + rrow,
+                     active, t);
 #pragma unroll
   for (int i = 0; i < PMAX; ++i)
     if (i < p)
-      row_c2r<T, NX, E>(w[1 + i], a.s_in + (2 + i) * a.fs_spec + rrow * a.Sx,
-                        a.s_in + (2 + i) * a.fs_spec + a.nyo + rrow, active, t, my, lt, tws);
+      row_load<T, NX, E>(w[1 + i], xn[1 + i], a.s_in + (2 + i) * a.fs_spec + rrow * a.Sx,
+                         a.s_in + (2 + i) * a.fs_spec + a.nyo + rrow, active, t);
+  row_c2r<T, NX, E>(w[0], xn[0], t, my, lt, tws);
+  row_c2r<T, NX, E>(bc, xn[FB], t, my, lt, tws);
+#pragma unroll
+  for (int i = 0; i < PMAX; ++i)
+    if (i < p) row_c2r<T, NX, E>(w[1 + i], xn[1 + i], t, my, lt, tws);
 
   double q[4] = {0.0, 0.0, 0.0, 0.0};
   const double cmean = *a.mean_c;

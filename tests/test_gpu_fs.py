@@ -53,13 +53,18 @@ SHAPES = [
     (2, (8, 4096), 2), (3, (16, 1024, 8), 2), (3, (8, 8, 1024), 1),
     # 2048-point rows
     (2, (2048, 64), 4),
+    # the register-form row pass with all five fields fixed at compile time
+    # (Nx = 4096; double also Nx = 2048), for both free energies
+    (2, (4096, 16), 4), (2, (4096, 8), 4, "poly"), (2, (2048, 16), 4, "poly"),
 ]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("ndim,n,p", SHAPES)
-def test_shapes_parity(ndim, n, p, prec):
+@pytest.mark.parametrize("ndim,n,p,fek", [s + (None,) if len(s) == 3 else s for s in SHAPES])
+def test_shapes_parity(ndim, n, p, fek, prec):
     fe = I.PAPER_FE if p % 2 == 0 else I.POLY_FE
+    if fek == "poly":
+        fe = I.POLY_FE
     dx = (1.0, 0.9, 1.1)[:ndim]
     cfg = I.make_config(ndim, n, dx, p, fe, M=5.0, kappa_c=3.0, L=4.0, kappa_eta=2.0)
     u0 = I.random_ic(cfg, seed=7, c0=0.5)

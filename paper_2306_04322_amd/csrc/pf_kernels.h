@@ -941,14 +941,19 @@ struct ColGeom {
 
 // Work order of the column pass (see col_kernel), the faster choice for
 // each case on MI355X: 0 = field group fastest over a contiguous run of
-// items per XCD (2D double), 1 = per-XCD chunks of tiles (2D float),
-// 2 = outer rows dealt to the XCDs round-robin (3D passes).
+// items per XCD (2D double of length below PF_COL_ORDER1_F64_MIN),
+// 1 = per-XCD chunks of tiles (2D float; 2D double of longer columns, whose
+// narrow tiles share cache lines that the chunk order keeps in one L2 while
+// they are used), 2 = outer rows dealt to the XCDs round-robin (3D passes).
 #ifndef PF_COL_ORDER3D
 #define PF_COL_ORDER3D 2
 #endif
-template <typename T>
+#ifndef PF_COL_ORDER1_F64_MIN
+#define PF_COL_ORDER1_F64_MIN 4096
+#endif
+template <typename T, int N>
 __host__ __device__ inline int col_order(int nouter) {
-  return nouter > 1 ? PF_COL_ORDER3D : (sizeof(T) == 4 ? 1 : 0);
+  return nouter > 1 ? PF_COL_ORDER3D : (sizeof(T) == 4 || N >= PF_COL_ORDER1_F64_MIN) ? 1 : 0;
 }
 
 // One work-group per (column tile, outer index, field group), plus, ahead of
@@ -970,7 +975,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots, int nqb
   using G = ColGeom<T, N>;
   constexpr int E = G::E, TEAM = G::TEAM, C = G::C;
   int L, g, tile, o;
-  const int order = col_order<T>(nouter);
+  const int order = col_order<T, N>(nouter);
   // blocks [0, nqb): Nyquist items, C outer rows of the Nyquist column each
   // (nqb is a multiple of 8, so the XCD of a regular block is unchanged)
   const int nqi = (nouter + C - 1) / C;  // Nyquist items per field group

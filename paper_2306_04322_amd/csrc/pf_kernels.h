@@ -19,10 +19,11 @@
 // it loads real rows or inverse-transforms x-spectra back to real rows
 // (C2R), optionally stores the real rows, evaluates the free-energy
 // derivative and forward-transforms (R2C) the right-hand-side combinations,
-// and accumulates double-precision sums.  rowpass_kernel (one wavefront
-// per transform, rows staged in LDS) is the main form; xpass_kernel (one
-// team of lanes per row, registers only) covers the shapes whose row
-// buffer does not fit LDS (Nx = 4096, double Nx = 2048).
+// and accumulates double-precision sums.  Two forms: rowpass_kernel (one
+// wavefront per transform, rows staged in an LDS row buffer) for rows of
+// 512 and 1024 points, and xpass_kernel (one team of lanes per row, all
+// fields of the row in registers) for shorter and longer rows (the launcher
+// in k_row.inc chooses; the LDS form only where its buffer fits).
 //
 // Column pass (col_kernel): transforms along a strided axis (y, or z in
 // 3D) for a tile of C consecutive x-spectrum columns.  Lanes are laid out

@@ -16,6 +16,8 @@ caught.  Trajectories (Algorithm 1; Eq. (12)-(15), (19)):
   w2     2D 1024^2, c + 4 eta, seeded uniform state, dt = 0.1, 200 steps
   paper  2D 1024^2, c + 4 eta, Eq. (4)-(5) state at dx = 1, dt = 0.01, 200 steps
   w3     3D 256^3,  c + 4 eta, seeded uniform state, dt = 0.1, 2 steps
+  fd3    3D 256^3,  c + 4 eta, seeded uniform state, two explicit FD steps
+         (Sec. 2.2) at the workload's FD step
   w5     3D 128^3,  c + 4 eta, seeded uniform state, dt = 0.1, 3 steps, then
          the discrete adjoint of those steps from a seeded terminal
          cotangent; stored are dJ/du^0 on sampled lines (with its per-field
@@ -41,6 +43,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 from oracle import adjoint as oadj  # noqa: E402
+from oracle import fd as ofd  # noqa: E402
 from oracle import fs as ofs  # noqa: E402
 from paper_2306_04322_amd import inputs as I  # noqa: E402
 
@@ -84,6 +87,9 @@ def trajectory(name):
     if name == "w3":
         cfg, w = I.workload_config("W3")
         return cfg, w["dt_fs"], 2, fp32_rounded(I.workload_ic(cfg, w))
+    if name == "fd3":
+        cfg, w = I.workload_config("W3")
+        return cfg, w["dt_fd"], 2, fp32_rounded(I.workload_ic(cfg, w))
     if name == "w5":
         cfg, w = I.workload_config("W5")
         return cfg, w["dt_fs"], 3, fp32_rounded(I.workload_ic(cfg, w))
@@ -129,7 +135,10 @@ def write(name):
         return write_adjoint(name)
     cfg, dt, steps, u0 = trajectory(name)
     t0 = time.time()
-    ref = ofs.fs_run(u0, cfg, dt, steps, workers=WORKERS)
+    if name == "fd3":
+        ref = ofd.fd_run(u0, cfg, dt, steps)
+    else:
+        ref = ofs.fs_run(u0, cfg, dt, steps, workers=WORKERS)
     np.savez(path_of(name),
              digest=np.array(source_digest()),
              dt=np.array(dt), steps=np.array(steps),
@@ -141,5 +150,5 @@ def write(name):
 
 
 if __name__ == "__main__":
-    for nm in (sys.argv[1:] or ["w2", "paper", "w3", "w5"]):
+    for nm in (sys.argv[1:] or ["w2", "paper", "w3", "fd3", "w5"]):
         write(nm)

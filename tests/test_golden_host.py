@@ -3,9 +3,9 @@
 The values are written by `tests/golden/make_fullsize_golden.py`, which runs
 only the oracle.  Here: the file was written by the current oracle and input
 module (source digest), it has the expected layout, and it satisfies a
-property of the method that holds at any size: the FS step never changes the
-k = 0 mode of c, so the sum of c over the grid equals that of the initial
-state (Eq. (14) at xi = 0)."""
+property of the method that holds at any size: neither the FS step (Eq. (14)
+at xi = 0) nor the FD step (the divergence form of Eq. (2)) changes the sum
+of c over the grid, so it equals that of the initial state."""
 
 import os
 import sys
@@ -18,7 +18,7 @@ sys.path.insert(0, os.path.join(HERE, "golden"))
 import make_fullsize_golden as G  # noqa: E402
 
 
-@pytest.mark.parametrize("name", ["w2", "paper", "w3"])
+@pytest.mark.parametrize("name", ["w2", "paper", "w3", "fd3"])
 def test_stored_values_current_and_consistent(name):
     z = np.load(G.path_of(name))
     assert str(z["digest"]) == G.source_digest(), "rerun make_fullsize_golden.py"

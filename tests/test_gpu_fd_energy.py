@@ -146,3 +146,22 @@ def test_fd_full_size_2d_1024(prec):
     got = s.get_fields()
     ref = ofd.fd_run(u0, cfg, w["dt_fd"], 2)
     assert max_rel(rel_l2(got, ref)) <= (1e-13 if prec == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("scheme", ["fs", "fd"])
+def test_energy_full_size_2d_1024(scheme, prec):
+    """The five scalars of pf_energy at the 2D throughput shape (1024^2,
+    c + 4 eta) against the oracle, in the launch configuration the benchmark
+    times."""
+    cfg, w = I.workload_config("W2")
+    u0 = I.workload_ic(cfg, w)
+    if prec == "f32":
+        u0 = fp32_rounded(u0)
+    announce("energy full 1024^2", scheme, prec)
+    s = _solver(cfg, prec, u0)
+    got = s.energy(scheme)
+    ref = oen.energy(u0, cfg, scheme)
+    tol = 1e-12 if prec == "f64" else 2e-6
+    for i in range(5):
+        assert abs(got[i] - ref[i]) <= tol * max(abs(ref[i]), 1e-3 * abs(ref[0])), (i, got, ref)

@@ -50,17 +50,17 @@ def _golden(name):
     return z
 
 
-def _run_and_compare(name, prec, chunks):
+def _run_and_compare(name, prec, chunks, scheme="fs"):
     gpu_or_fail()
     from paper_2306_04322_amd.pfspec import Solver
     z = _golden(name)
     cfg, dt, steps, u0 = G.trajectory(name)
     assert sum(chunks) == int(z["steps"]) == steps
-    announce("fs full", name, cfg["n"], "steps", steps, prec)
+    announce(scheme + " full", name, cfg["n"], "steps", steps, prec)
     s = Solver(cfg, prec)
     s.set_fields(u0)
     for k in chunks:
-        s.step_fs(dt, k)
+        (s.step_fs if scheme == "fs" else s.step_fd)(dt, k)
     got = s.get_fields()
     del s
     F = got.shape[0]
@@ -112,6 +112,18 @@ def test_w3_256_random_ic(prec):
     assert all(e is not None for e in errs)
     assert max_rel(errs) <= TOL[prec]
     assert max(e for e in rms_err) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fd3_256_two_steps(prec):
+    """The explicit FD comparison step at the 3D throughput shape (256^3,
+    c + 4 eta, the workload's FD step): two steps, the marching kernels with
+    LDS plane tiles that the benchmark times."""
+    errs, fl, mean_err, rms_err = _run_and_compare("fd3", prec, (2,), scheme="fd")
+    assert all(e is not None for e in errs)
+    assert max_rel(errs) <= (1e-13 if prec == "f64" else 1e-6)
+    assert max(e for e in rms_err) <= (1e-13 if prec == "f64" else 1e-6)
+    assert mean_err[0] <= (1e-14 if prec == "f64" else 1e-6)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

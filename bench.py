@@ -303,6 +303,15 @@ def main(argv=None):
     e32 = rel_l2(u32, u64)
     errors = {"f32_vs_f64_gpu": {"steps": n_all, "rel_l2_per_field": e32, "max": max_err(e32)}}
     log("fp32 vs fp64 GPU after %d steps: %s" % (n_all, e32))
+    # the same comparison where all five fields stay non-trivial: the Eq. (4)-(5)
+    # state on the same grid (dx = 1), dt = 0.01, 200 steps, both precisions from
+    # the FP32-rounded state
+    cfgp = I.make_config(2, 1024, 1.0, 4, I.PAPER_FE)
+    up = np.asarray(I.paper_ic_2d(cfgp), dtype=np.float32).astype(np.float64)
+    ep = rel_l2(run_fields(cfgp, "f32", up, 0.01, 200, torch), run_fields(cfgp, "f64", up, 0.01, 200, torch))
+    errors["f32_vs_f64_gpu_eq4_5_state"] = {"steps": 200, "dt": 0.01, "rel_l2_per_field": ep,
+                                            "max": max_err(ep)}
+    log("fp32 vs fp64 GPU, Eq. (4)-(5) state, 200 steps: %s" % ep)
 
     out = {"metric": METRIC, "value": value, "unit": "grid-pt updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,

@@ -16,6 +16,8 @@ caught.  Trajectories (Algorithm 1; Eq. (12)-(15), (19)):
   w2     2D 1024^2, c + 4 eta, seeded uniform state, dt = 0.1, 200 steps
   paper  2D 1024^2, c + 4 eta, Eq. (4)-(5) state at dx = 1, dt = 0.01, 200 steps
   w3     3D 256^3,  c + 4 eta, seeded uniform state, dt = 0.1, 2 steps
+  w2_4k  2D 4096^2, c + 4 eta, seeded uniform state, dt = 0.1, 2 steps (the
+         largest 2D grid the benchmark times; rows and columns of 4096)
   fd3    3D 256^3,  c + 4 eta, seeded uniform state, two explicit FD steps
          (Sec. 2.2) at the workload's FD step
   w5     3D 128^3,  c + 4 eta, seeded uniform state, dt = 0.1, 3 steps, then
@@ -26,7 +28,7 @@ caught.  Trajectories (Algorithm 1; Eq. (12)-(15), (19)):
 Every run starts from the FP32-rounded initial state, so one trajectory
 serves the FP32 and the FP64 GPU paths.
 
-Usage (from the repository root; about 17 minutes on 8 host cores):
+Usage (from the repository root; about 20 minutes on 8 host cores):
     python tests/golden/make_fullsize_golden.py [w2 paper w3]
 """
 
@@ -53,6 +55,8 @@ WORKERS = 5
 ROWS_2D = (0, 1, 517, 1023)
 LINES_3D = ((0, 0), (0, 255), (1, 128), (77, 3), (128, 128), (200, 31),
             (254, 200), (255, 255))
+# (y) lines of the 4096^2 grid
+ROWS_4K = (0, 2049, 4095)
 # (z, y) lines of the 128^3 adjoint grid
 LINES_W5 = ((0, 0), (0, 127), (1, 64), (45, 3), (64, 64), (100, 31), (127, 127))
 # seed of the terminal cotangent dJ/du^T of the adjoint case
@@ -87,6 +91,9 @@ def trajectory(name):
     if name == "w3":
         cfg, w = I.workload_config("W3")
         return cfg, w["dt_fs"], 2, fp32_rounded(I.workload_ic(cfg, w))
+    if name == "w2_4k":
+        cfg, w = I.workload_config("W2", n=4096)
+        return cfg, w["dt_fs"], 2, fp32_rounded(I.workload_ic(cfg, w))
     if name == "fd3":
         cfg, w = I.workload_config("W3")
         return cfg, w["dt_fd"], 2, fp32_rounded(I.workload_ic(cfg, w))
@@ -105,7 +112,8 @@ def w5_lambda_T(cfg):
 def sample(u, ndim):
     """The stored lines of the fields u (F, ...): (F, lines, Nx)."""
     if ndim == 2:
-        return np.ascontiguousarray(u[:, list(ROWS_2D), :])
+        rows = ROWS_2D if u.shape[-1] == 1024 else ROWS_4K
+        return np.ascontiguousarray(u[:, list(rows), :])
     lines = LINES_3D if u.shape[-1] == 256 else LINES_W5
     return np.ascontiguousarray(np.stack([u[:, z, y, :] for z, y in lines], axis=1))
 
@@ -150,5 +158,5 @@ def write(name):
 
 
 if __name__ == "__main__":
-    for nm in (sys.argv[1:] or ["w2", "paper", "w3", "fd3", "w5"]):
+    for nm in (sys.argv[1:] or ["w2", "paper", "w3", "w2_4k", "fd3", "w5"]):
         write(nm)

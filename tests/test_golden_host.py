@@ -18,14 +18,15 @@ sys.path.insert(0, os.path.join(HERE, "golden"))
 import make_fullsize_golden as G  # noqa: E402
 
 
-@pytest.mark.parametrize("name", ["w2", "paper", "w3", "fd3"])
+@pytest.mark.parametrize("name", ["w2", "paper", "w3", "w2_4k", "fd3"])
 def test_stored_values_current_and_consistent(name):
     z = np.load(G.path_of(name))
     assert str(z["digest"]) == G.source_digest(), "rerun make_fullsize_golden.py"
     cfg, dt, steps, u0 = G.trajectory(name)
     assert float(z["dt"]) == dt and int(z["steps"]) == steps
     F = 1 + cfg["p"]
-    nlines = len(G.ROWS_2D) if cfg["ndim"] == 2 else len(G.LINES_3D)
+    nlines = (len(G.ROWS_2D) if cfg["n"][0] == 1024 else len(G.ROWS_4K)) if cfg["ndim"] == 2 \
+        else len(G.LINES_3D)
     assert z["sample"].shape == (F, nlines, cfg["n"][0])
     assert np.all(np.isfinite(z["sample"]))
     s0 = u0[0].sum()

@@ -20,7 +20,8 @@ throughput workload the order parameters vanish within a few steps at
 dt = 0.1 (dt L d2f/deta2 = 1 at eta = 0), in the oracle and on the GPU alike.
 The 1024^2 run of the Eq. (4)-(5) state keeps all five fields non-trivial.
 
-The discrete adjoint is checked at the differentiable 3D shape (128^3,
+Two steps at 4096^2 cover the largest 2D grid the benchmark times.  The
+discrete adjoint is checked at the differentiable 3D shape (128^3,
 c + 4 eta) over three steps in two checkpoint segments (2 + 1 steps): the
 gradient with respect to the initial fields on the sampled lines and as
 whole-field aggregates, and the four parameter gradients."""
@@ -112,6 +113,17 @@ def test_w3_256_random_ic(prec):
     assert all(e is not None for e in errs)
     assert max_rel(errs) <= TOL[prec]
     assert max(e for e in rms_err) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_w2_4096_two_steps(prec):
+    """2D 4096^2, c + 4 eta, seeded uniform state, two steps: the register-form
+    row pass and the 4096-point column tiles at the size the benchmark times."""
+    errs, fl, mean_err, rms_err = _run_and_compare("w2_4k", prec, (2,))
+    assert all(e is not None for e in errs)
+    assert max_rel(errs) <= TOL[prec]
+    assert max(e for e in rms_err) <= TOL[prec]
+    assert mean_err[0] <= (1e-14 if prec == "f64" else 1e-6)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

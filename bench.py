@@ -351,6 +351,7 @@ def main(argv=None):
             tb = time_fs(sb, dt, 200, 0, torch)
             reps_ms.append(1e3 * tb / 200)
         extras["fs_2d_1024_f32_6x200"] = {"mean_ms_per_step": sum(reps_ms) / 6,
+                                          "median_ms_per_step": float(np.median(reps_ms)),
                                           "min_ms_per_step": min(reps_ms),
                                           "max_ms_per_step": max(reps_ms)}
         del sb
@@ -366,8 +367,13 @@ def main(argv=None):
         extras["fs_2d_1024_f64"] = {"value": v64, "ms_per_step": 1e3 * t64 / n64,
                                     "fp32_over_fp64": value / v64,
                                     "mean_ms_per_step_6x200": sum(reps64) / 6,
+                                    "median_ms_per_step_6x200": float(np.median(reps64)),
                                     "fp32_over_fp64_6x200": (sum(reps64) / 6)
                                     / extras["fs_2d_1024_f32_6x200"]["mean_ms_per_step"],
+                                    # the same on the medians of the six batches (one
+                                    # disturbed batch moves the means)
+                                    "fp32_over_fp64_6x200_median": float(np.median(reps64))
+                                    / extras["fs_2d_1024_f32_6x200"]["median_ms_per_step"],
                                     "passes": pass_rates(s64, cfg, "f64", reps)}
         log("fp64 %.3f ms/step; fp32/fp64 = %.2f" % (1e3 * t64 / n64, value / v64))
         del s64

@@ -1068,6 +1068,16 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots, int nqb
   const T kc = a.kcol[active ? col : 0] + (a.kouter ? a.kouter[active ? orow : 0] : T(0));
   Twiddles<T, N, E> tws;
   tws.load(t, a.tw, 1);
+  // the axis part of |xi|^2 of this lane's elements; the steady update reads
+  // it before the transforms (a work-group barrier keeps later reads from
+  // moving up), the others where it is used
+  constexpr bool KPRE = MODE == COL_UPDATE;
+  T kax[E];
+  if constexpr (KPRE) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) kax[m] = a.kaxis[t + TEAM * m];
+  }
+  auto kaxis = [&](int m) -> T { return KPRE ? kax[m] : a.kaxis[t + TEAM * m]; };
 
   c2<T> v[E];
   if constexpr (MODE == COL_FWD || MODE == COL_INV) {
@@ -1110,7 +1120,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots, int nqb
       }
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const T k2 = kc + a.kaxis[t + TEAM * m];
+        const T k2 = kc + kaxis(m);
         const T D = recip<T>(T(1) + a.dtMkc * k2 * k2);
         const T sk = a.dtM * k2;
         v[m] = mk<T>((v[m].x - sk * gg[m].x) * D, (v[m].y - sk * gg[m].y) * D);
@@ -1130,7 +1140,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots, int nqb
       par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const T k2 = kc + a.kaxis[t + TEAM * m];
+        const T k2 = kc + kaxis(m);
         const T D = a.invP * recip<T>(T(1) + a.dtLke * k2);
         v[m] = mk<T>(v[m].x * D, v[m].y * D);
       }
@@ -1145,7 +1155,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots, int nqb
       par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const T k2 = kc + a.kaxis[t + TEAM * m];
+        const T k2 = kc + kaxis(m);
         const T x = a.dtMkc * k2 * k2;
         const T D = a.invP * recip<T>(T(1) + x);
         bb[m] = mk<T>(v[m].x * D * k2, v[m].y * D * k2);
@@ -1161,7 +1171,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots, int nqb
       par = team_fft<T, N, E, false, C>(v, t, my, tws, my2, par);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const T k2 = kc + a.kaxis[t + TEAM * m];
+        const T k2 = kc + kaxis(m);
         const T y = a.dtLke * k2;
         const T D = a.invP * y * recip<T>(T(1) + y);
         v[m] = mk<T>(v[m].x * D, v[m].y * D);
@@ -1178,7 +1188,7 @@ col_kernel(ColArgs<T> a, int tiles, int nouter, int ngroups, int nslots, int nqb
     if (active) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const double k2 = double(kc) + double(a.kaxis[t + TEAM * m]);
+        const double k2 = double(kc) + double(kaxis(m));
         const double re = double(v[m].x), im = double(v[m].y);
         acc[g == 0 ? 0 : 1] += wcol * k2 * (re * re + im * im);
       }

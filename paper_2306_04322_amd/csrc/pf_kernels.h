@@ -56,7 +56,7 @@
 #define PF_ROW_ROWS_LONG 4  // rows per row-pass work-group, float, Nx = 1024
 #endif
 #ifndef PF_ROW_MULT_2048
-#define PF_ROW_MULT_2048 2  // row-pass work-group multiple, float, Nx = 2048
+#define PF_ROW_MULT_2048 2  // LDS-form work-group multiple, float, Nx = 2048 (now the adjoint only)
 #endif
 #ifndef PF_ROW_MULT_SHORT
 #define PF_ROW_MULT_SHORT 1  // row-pass work-group multiple, float, Nx < 1024 (2 and 4 measured slower)
@@ -199,6 +199,10 @@ __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* __restrict__ dst, c2<T>
   __syncthreads();
 }
 
+// Row pass, register form: one team of NX/(2E) lanes per row holds all F
+// fields of its row in registers (the pointwise phase needs no LDS), and the
+// x-spectra of all fields are loaded before the first transform.  Used for
+// rows of up to 256 points and from 2048 points (the launcher chooses).
 // FX >= 0 fixes the flags apart from X_STORE_REAL, and FEK >= 0 the
 // free-energy kind with p = PMAX, as in rowpass_kernel below.
 template <typename T, int NX, int PMAX, int FX = -1, int FEK = -1>
@@ -373,8 +377,10 @@ __device__ __forceinline__ void wave_c2r_pre(c2<T>* v, const c2<T>* __restrict__
 // buffer.  Phase 3: each wavefront forward-transforms (R2C) one (row,
 // output) slot and stores its x-spectrum.  FFT exchanges inside a phase are
 // wavefront-local, so only the two phase boundaries synchronise the
-// work-group.  Used when a transform fits one wavefront (Nx <= 2048) and
-// the row buffer fits LDS; otherwise xpass_kernel above.
+// work-group.  Usable when a transform fits one wavefront (Nx <= 2048) and
+// the row buffer fits LDS; the forward launcher takes it for 512 and 1024
+// points, the adjoint wherever it is usable (else xpass_kernel /
+// adj_row_kernel).
 // SM selects the form for grids with few rows: one row per work-group and
 // just enough wavefronts for its F transforms, which spreads a small grid
 // over more compute units than 1024-point work-groups would.
@@ -392,7 +398,8 @@ struct RGeom {
   // (1024/Nx rows or one row, PF_ROW_NW wavefronts).  Meant to spread the
   // transforms of rows whose F does not divide over the wavefronts (F = 5
   // over 4) evenly over the CU's SIMDs; measured faster at Nx = 1024 (four
-  // rows) and 2048 (two rows) only.
+  // rows) and 2048 (two rows) only.  (The forward row pass now takes the
+  // register form at 2048 points; the adjoint row pass keeps this one.)
   static constexpr int BASE_ROWS = SM ? 1 : (NX >= 1024 ? 1 : 1024 / NX);
   static constexpr int MULT_WANT = NX == 2048 ? PF_ROW_MULT_2048 : NX == 1024 ? PF_ROW_ROWS_LONG : PF_ROW_MULT_SHORT;
   static constexpr bool MULTI = !SM && NX <= 2048 && sizeof(T) == 4 && PF_ROW_NW > 0 && MULT_WANT > 1 &&

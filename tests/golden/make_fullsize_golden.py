@@ -111,10 +111,11 @@ def w5_lambda_T(cfg):
 
 def sample(u, ndim):
     """The stored lines of the fields u (F, ...): (F, lines, Nx)."""
+    n = u.shape[-1]
     if ndim == 2:
-        rows = ROWS_2D if u.shape[-1] == 1024 else ROWS_4K
+        rows = {1024: ROWS_2D, 4096: ROWS_4K}[n]
         return np.ascontiguousarray(u[:, list(rows), :])
-    lines = LINES_3D if u.shape[-1] == 256 else LINES_W5
+    lines = {256: LINES_3D, 128: LINES_W5}[n]
     return np.ascontiguousarray(np.stack([u[:, z, y, :] for z, y in lines], axis=1))
 
 

@@ -221,6 +221,9 @@ class Solver:
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.shape = field_shape(cfg)
+        # the library's destroy entry, held here so that __del__ still has it
+        # while the interpreter tears down module globals at exit
+        self._destroy = _lib.pf_destroy
         self.h = pf_create(make_config(cfg, precision, self.stream.cuda_stream))
         self.fields = torch.zeros(self.shape, dtype=self.dtype, device=self.device)
         nb = pf_workspace_bytes(self.h)
@@ -229,12 +232,13 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None:
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and destroy is not None:
             try:
                 self.torch.cuda.synchronize(self.device)
             except Exception:
                 pass
-            pf_destroy(h)
+            destroy(h)
             self.h = None
 
     def set_fields(self, u):

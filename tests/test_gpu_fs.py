@@ -56,6 +56,8 @@ SHAPES = [
     # the register-form row pass with all five fields fixed at compile time
     # (Nx = 4096; double also Nx = 2048), for both free energies
     (2, (4096, 16), 4), (2, (4096, 8), 4, "poly"), (2, (2048, 16), 4, "poly"),
+    # eight order parameters (the largest p) on long rows in both forms
+    (2, (1024, 16), 8), (2, (4096, 8), 8), (3, (256, 16, 8), 8),
 ]
 
 

@@ -47,10 +47,12 @@ def _gpu_adjoint(cfg, prec, u0, lam_T, dt, nsteps, K):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("case", ["paper2d", "poly2d", "paper3d", "paper3d_cube", "fd2"])
+@pytest.mark.parametrize("case", ["paper2d", "poly2d", "paper3d", "paper3d_cube", "fd2", "paper2d_p8"])
 def test_adjoint_matches_oracle(case, prec):
     if case == "paper2d":
         cfg = _cfg(2, 32, 2)
+    elif case == "paper2d_p8":
+        cfg = _cfg(2, (64, 16), 8)
     elif case == "poly2d":
         cfg = _cfg(2, (16, 32), 3, I.POLY_FE)
     elif case == "paper3d":

@@ -78,9 +78,12 @@ def test_fd_shapes_parity(ndim, n, p, prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("scheme", ["fs", "fd"])
-@pytest.mark.parametrize("case", ["WO", "rand2d", "rand3d", "rand3d_wide", "poly"])
+@pytest.mark.parametrize("case", ["WO", "rand2d", "rand3d", "rand3d_wide", "poly", "rand2d_p8"])
 def test_energy_parity(case, scheme, prec):
-    if case == "WO":
+    if case == "rand2d_p8":
+        cfg = I.make_config(2, (64, 32), (1.0, 0.8), 8, I.PAPER_FE, **DISTINCT)
+        u0 = I.random_ic(cfg, 7)
+    elif case == "WO":
         cfg, w = I.workload_config("WO")
         u0 = I.workload_ic(cfg, w)
     elif case == "rand2d":

@@ -114,6 +114,31 @@ def pass_rates(solver, cfg, prec, reps):
     return out
 
 
+def passes_3d(solver, prec, dt, steps=10):
+    """Per-pass times of the 3D 256^3 FS step and the rates on each pass's
+    compulsory bytes (F = 5 x-spectra in and out; the z update one more each
+    way for the carried c spectrum).  Row pass and z update: pf_time_pass
+    (steady-state pass launched back to back between two events); the two y
+    passes: the per-launch events of `steps` steps (pf_profile_*) less the z
+    updates among them."""
+    from paper_2306_04322_amd import pfspec as PF
+    s = 4 if prec == "f32" else 8
+    half = 256 * 256 * 129 * 2 * s
+    row_us = 1e3 * PF.pf_time_pass(solver.h, 0, 20)
+    z_us = 1e3 * PF.pf_time_pass(solver.h, 1, 20)
+    PF.pf_profile_enable(solver.h, True)
+    solver.step_fs(dt, steps)
+    n_col, ms_col = PF.pf_profile_read(solver.h, PF.PROF_COL)
+    PF.pf_profile_enable(solver.h, False)
+    y_us = (1e3 * ms_col - steps * z_us) / max(1, n_col - steps)
+    out = {}
+    for name, us, nb in (("row", row_us, 10 * half), ("y_forward_or_inverse", y_us, 10 * half),
+                         ("z_update", z_us, 12 * half)):
+        out[name] = {"avg_launch_us": round(us, 2), "compulsory_bytes_per_launch": nb,
+                     "compulsory_GBs": round(nb / (us * 1e-6) / 1e9, 1)}
+    return out
+
+
 def time_fs(solver, dt, steps, warmup, torch):
     if warmup:
         solver.step_fs(dt, warmup)
@@ -428,7 +453,8 @@ def main(argv=None):
             extras["fs_3d_256_" + prec] = {
                 "value": P3 * n3 / t3, "ms_per_step": 1e3 * t3 / n3,
                 "step_frac_9Fs": round(P3 * n3 / t3 * 9 * 5 * (4 if prec == "f32" else 8)
-                                       / (HBM_PEAK_GBS * 1e9), 4)}
+                                       / (HBM_PEAK_GBS * 1e9), 4),
+                "passes": passes_3d(s3, prec, w3["dt_fs"])}
             log("3D %s %.3f ms/step" % (prec, 1e3 * t3 / n3))
             if prec == "f32":
                 s3.step_fd(w3["dt_fd"], 10)

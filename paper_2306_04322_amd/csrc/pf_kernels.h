@@ -438,7 +438,7 @@ rowpass_kernel(XArgs<T> a) {
   const int unit = lane / TEAM;
   const int t = lane - unit * TEAM;
   const int row0 = blockIdx.x * ROWS;
-  const int F = a.F;
+  const int F = FEK >= 0 ? PMAX + 1 : a.F;  // the fixed-kind instantiations have p = PMAX
   const int p = F - 1;
   // the store flag stays a run-time choice even in the fixed instantiations,
   // so a recomputation that also stores the states runs the same arithmetic
@@ -450,7 +450,10 @@ rowpass_kernel(XArgs<T> a) {
 
   // phase 1: real rows into the row buffer
   if (flags & X_LOAD_REAL) {
+    // (with F fixed the trip count is a constant and the loads of all
+    // iterations can be issued before the first store)
     const int n2 = ROWS * F * NH;
+#pragma unroll
     for (int q = tid; q < n2; q += WG) {
       const int x2 = q % NH;
       const int rf = q / NH;

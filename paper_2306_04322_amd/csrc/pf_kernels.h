@@ -626,7 +626,8 @@ struct AGeom {
   static constexpr int REGION = lds_span(NH) + 1;
 };
 
-template <typename T, int NX, int PMAX>
+// FIXF: F = PMAX + 1 at compile time.
+template <typename T, int NX, int PMAX, bool FIXF = false>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, AGeom<T, NX, PMAX>::WG)))
 adj_row_kernel(AdjArgs<T> a) {
   using G = AGeom<T, NX, PMAX>;
@@ -641,7 +642,7 @@ adj_row_kernel(AdjArgs<T> a) {
   const bool active = row < a.rows;
   const long long rrow = active ? row : 0;
   c2<T>* my = lds + team * G::REGION;
-  const int F = a.F;
+  const int F = FIXF ? PMAX + 1 : a.F;
   const int p = F - 1;
   Twiddles<T, G::NH, E> tws;
   tws.load(t, a.twx, 2);
@@ -739,7 +740,8 @@ adj_row_kernel(AdjArgs<T> a) {
 // structure and geometry).  Slots: 0 = e_c, 1 = b_c, 2 + i = e_i; the
 // pointwise phase overwrites slots 0 and 2 + i with lambda^n for the
 // forward transforms of phase 3.
-template <typename T, int NX, int PMAX>
+// FIXF: F = PMAX + 1 at compile time.
+template <typename T, int NX, int PMAX, bool FIXF = false>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, RGeom<T, NX, PMAX>::WG)))
 adjrow_kernel(AdjArgs<T> a) {
   using G = RGeom<T, NX, PMAX>;
@@ -754,7 +756,7 @@ adjrow_kernel(AdjArgs<T> a) {
   const int unit = lane / TEAM;
   const int t = lane - unit * TEAM;
   const int row0 = blockIdx.x * ROWS;
-  const int F = a.F;
+  const int F = FIXF ? PMAX + 1 : a.F;
   const int p = F - 1;
   Twiddles<T, NH, E> tws;
   tws.load(t, a.twx, 2);

@@ -150,12 +150,14 @@ __device__ __forceinline__ long long fd_first_point(int bands) {
 }
 
 // mu = df/dc - kappa_c lap(c);  eta_i' = eta_i - dt L (df/deta_i - kappa_eta lap(eta_i))
-template <typename T, int PMAX, int V>
+// FIXF: all PMAX order parameters in use (p fixed at compile time), as in
+// the mu kernels below.
+template <typename T, int PMAX, int V, bool FIXF = false>
 __global__ void __launch_bounds__(256) fd_mu_kernel(FdArgs<T> a, int bands) {
   const long long i0 = fd_first_point<V>(bands);
   if (i0 >= a.P) return;
   const NbV n = neighbours_vec<T, V>(a, i0);
-  const int p = a.F - 1;
+  const int p = FIXF ? PMAX : a.F - 1;
   const FdVec<T, V> cc = ld_vec<T, V>(a.in + i0);
   FdVec<T, V> ce[PMAX];
 #pragma unroll
@@ -257,11 +259,11 @@ __device__ __forceinline__ bool zcol(const FdArgs<T>& a, int zb, ZCol& q) {
   return true;
 }
 
-template <typename T, int PMAX, int V>
+template <typename T, int PMAX, int V, bool FIXF = false>
 __global__ void __launch_bounds__(256) fd_mu_z_kernel(FdArgs<T> a, int zb) {
   ZCol q;
   if (!zcol<T, V>(a, zb, q)) return;
-  const int p = a.F - 1;
+  const int p = FIXF ? PMAX : a.F - 1;
   FdVec<T, V> m[PMAX + 1], c[PMAX + 1], n[PMAX + 1];
   const long long zm0 = (long long)((q.z0 - 1) & (a.nz - 1)) * q.plane + q.rest;
   const long long zc0 = (long long)q.z0 * q.plane + q.rest;
@@ -416,13 +418,13 @@ __device__ __forceinline__ void stage_plane(T* lds, const T* __restrict__ base, 
   }
 }
 
-template <typename T, int PMAX, int V>
+template <typename T, int PMAX, int V, bool FIXF = false>
 __global__ void __launch_bounds__(FD_ZL_WG) fd_mu_zl_kernel(FdArgs<T> a, int zb) {
   extern __shared__ __align__(16) unsigned char fd_lds_raw[];
   T* lds = reinterpret_cast<T*>(fd_lds_raw);
   ZTile q;
   if (!ztile<T, V>(a, zb, q)) return;
-  const int p = a.F - 1;
+  const int p = FIXF ? PMAX : a.F - 1;
   const int tsz = (q.R + 2) * a.nx;
   const long long rest = (long long)(q.y0 + q.r) * a.nx + q.x0;
   FdVec<T, V> m[PMAX + 1], c[PMAX + 1], n[PMAX + 1];
@@ -574,6 +576,7 @@ static int fd_bands(const FdArgs<T>& a) {
 template <typename T, int PMAX, int V>
 static int fd_go_v(int which, const FdArgs<T>& a, hipStream_t s) {
   const long long nv = a.P / V;  // nx >= 8 is a multiple of V
+  const bool full = a.F == PMAX + 1;  // the mu kernel's p fixed at compile time
   const int bands = fd_bands(a);
   if (PF_FD_ZMARCH && a.ndim == 3 && !bands) {
     const int zb = a.nz < PF_FD_ZB ? a.nz : PF_FD_ZB;  // both powers of two
@@ -588,7 +591,9 @@ static int fd_go_v(int which, const FdArgs<T>& a, hipStream_t s) {
     if (PF_FD_ZLDS && R >= 2 && R <= a.ny && lds_mu <= (160u << 10) / 3) {
       const long long nb = (long long)(a.ny / R) * (a.nz / zb);
       const int grid = int((nb + 7) / 8 * 8);
-      if (which == 0)
+      if (which == 0 && full)
+        hipLaunchKernelGGL((fd_mu_zl_kernel<T, PMAX, V, true>), dim3(grid), dim3(FD_ZL_WG), lds_mu, s, a, zb);
+      else if (which == 0)
         hipLaunchKernelGGL((fd_mu_zl_kernel<T, PMAX, V>), dim3(grid), dim3(FD_ZL_WG), lds_mu, s, a, zb);
       else
         hipLaunchKernelGGL((fd_c_zl_kernel<T, V>), dim3(grid), dim3(FD_ZL_WG),
@@ -596,13 +601,15 @@ static int fd_go_v(int which, const FdArgs<T>& a, hipStream_t s) {
       return grid;
     }
     const int grid = int((nv / zb + 255) / 256 + 7) / 8 * 8;
-    if (which == 0) hipLaunchKernelGGL((fd_mu_z_kernel<T, PMAX, V>), dim3(grid), dim3(256), 0, s, a, zb);
+    if (which == 0 && full) hipLaunchKernelGGL((fd_mu_z_kernel<T, PMAX, V, true>), dim3(grid), dim3(256), 0, s, a, zb);
+    else if (which == 0) hipLaunchKernelGGL((fd_mu_z_kernel<T, PMAX, V>), dim3(grid), dim3(256), 0, s, a, zb);
     else hipLaunchKernelGGL((fd_c_z_kernel<T, V>), dim3(grid), dim3(256), 0, s, a, zb);
     return grid;
   }
   int grid = int((nv + 255) / 256);
   if (bands) grid = (grid + 7) / 8 * 8;
-  if (which == 0) hipLaunchKernelGGL((fd_mu_kernel<T, PMAX, V>), dim3(grid), dim3(256), 0, s, a, bands);
+  if (which == 0 && full) hipLaunchKernelGGL((fd_mu_kernel<T, PMAX, V, true>), dim3(grid), dim3(256), 0, s, a, bands);
+  else if (which == 0) hipLaunchKernelGGL((fd_mu_kernel<T, PMAX, V>), dim3(grid), dim3(256), 0, s, a, bands);
   else hipLaunchKernelGGL((fd_c_kernel<T, V>), dim3(grid), dim3(256), 0, s, a, bands);
   return grid;
 }

@@ -73,6 +73,9 @@
 #ifndef PF_COL_WG_MAX_LONG
 #define PF_COL_WG_MAX_LONG 1024  // largest column work-group, float, length 4096 (2-column tiles)
 #endif
+#ifndef PF_XROW_E8_F64_MIN
+#define PF_XROW_E8_F64_MIN 4096  // double rows from this length: 8 elements per lane (measured: 4096 faster, 2048 slower)
+#endif
 #ifndef PF_XROW_MIN_WAVES
 #define PF_XROW_MIN_WAVES 2  // register budget, register-form row pass (waves per SIMD)
 #endif
@@ -121,7 +124,8 @@ struct XArgs {
 template <typename T, int NX, int PMAX>
 struct XGeom {
   static constexpr int NH = NX / 2;
-  static constexpr int EW = (sizeof(T) == 8 || PMAX > 4) ? 4 : 8;
+  static constexpr int EW = (sizeof(T) == 8 && NX >= PF_XROW_E8_F64_MIN && PMAX <= 4) ? 8
+                          : (sizeof(T) == 8 || PMAX > 4) ? 4 : 8;
   static constexpr int E = NH < EW ? NH : EW;
   static constexpr int TEAM = NH / E;
   static constexpr int ROWS = TEAM >= 64 ? 1 : 64 / TEAM;
@@ -130,7 +134,7 @@ struct XGeom {
   // register budget of the fixed-flag instantiations: two work-groups per
   // SIMD where a work-group has at most one wavefront per SIMD (with up to
   // five fields; eight order parameters would spill)
-  static constexpr int MIN_WAVES = (WG <= 256 && PMAX <= 4) ? PF_XROW_MIN_WAVES : 1;
+  static constexpr int MIN_WAVES = (WG <= 256 && PMAX <= 4 && !(sizeof(T) == 8 && E == 8)) ? PF_XROW_MIN_WAVES : 1;
 };
 
 // Loads of one x-spectrum row for row_c2r: v[m] = X_k, k = t + TEAM m, and

@@ -58,6 +58,8 @@ SHAPES = [
     (2, (4096, 16), 4), (2, (4096, 8), 4, "poly"), (2, (2048, 16), 4, "poly"),
     # eight order parameters (the largest p) on long rows in both forms
     (2, (1024, 16), 8), (2, (4096, 8), 8), (3, (256, 16, 8), 8),
+    # 3D grids with the longest rows 3D accepts (1024 points, the LDS form)
+    (3, (1024, 8, 8), 2), (3, (1024, 16, 8), 4),
 ]
 
 

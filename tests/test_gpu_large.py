@@ -12,7 +12,14 @@ quantities below:
   Here lam = -sum_d (2 - 2 cos(2 pi m_d / N_d)) / dx_d^2 is the symbol of the
   periodic 7-point Laplacian.
 The expected fields come from torch.fft (rocFFT) in double precision on the
-GPU. The library under test shares nothing with it."""
+GPU. The library under test shares nothing with it.
+
+The five energy scalars of the seeded state are checked on the same grid.
+With f = 0 the chemical part vanishes. The gradient parts of Eq. (1) are
+(kappa / 2) dV (1/P) sum_k |xi_k|^2 |v^_k|^2 in the spectral form (Parseval,
+over the full spectrum: interior x-modes of the half spectrum count twice).
+In the FD form they are (kappa / 2) dV sum_x sum_d ((v(x + e_d) - v(x)) / dx_d)^2.
+The mass is dV sum_x c."""
 
 import numpy as np
 import pytest
@@ -52,6 +59,31 @@ def _errors(fields, u, mults, torch):
     return out
 
 
+def _energy_ref(u, torch, dev):
+    """{scheme: [E_total, E_chem, E_grad_c, E_grad_eta, mass]} of the fields u
+    (float64 device tensor) with f = 0."""
+    dV = DX[0] * DX[1] * DX[2]
+    P = u[0].numel()
+    k2 = _symbol(lambda m, n, h: (2 * np.pi * m / (n * h)) ** 2, torch, dev)
+    w = torch.full((N[0] // 2 + 1,), 2.0, dtype=torch.float64, device=dev)
+    w[0] = w[-1] = 1.0  # the x-modes 0 and Nx/2 appear once in the full spectrum
+    wk2 = k2 * w
+    del k2
+    fs, fd = [], []
+    for f in range(u.shape[0]):
+        fs.append(float(torch.sum(wk2 * torch.fft.rfftn(u[f]).abs() ** 2)) * dV / P)
+        sq = 0.0
+        for axis, h in ((2, DX[0]), (1, DX[1]), (0, DX[2])):
+            sq += float(torch.sum(((torch.roll(u[f], -1, dims=axis) - u[f]) / h) ** 2)) * dV
+        fd.append(sq)
+    mass = float(torch.sum(u[0])) * dV
+    out = {}
+    for sch, g in (("fs", fs), ("fd", fd)):
+        gc, ge = 0.5 * KC * g[0], 0.5 * KE * sum(g[1:])
+        out[sch] = [gc + ge, 0.0, gc, ge, mass]
+    return out
+
+
 @pytest.mark.parametrize("prec,p", [("f64", 2), ("f32", 4)])
 def test_largest_grid_linear_fs_and_fd(prec, p):
     torch = gpu_or_fail()
@@ -67,9 +99,18 @@ def test_largest_grid_linear_fs_and_fd(prec, p):
     tol = 1e-12 if prec == "f64" else 1e-6
     steps = 3
 
+    announce("largest grid, energy", N, prec, "F =", 1 + p)
+    s.set_fields(u)
+    ref = _energy_ref(u, torch, dev)
+    etol = 1e-10 if prec == "f64" else 1e-5
+    for sch in ("fs", "fd"):
+        got = s.energy(sch)
+        assert got[1] == 0.0, (sch, got)
+        for i in (0, 2, 3, 4):
+            assert abs(got[i] - ref[sch][i]) <= etol * abs(ref[sch][i]), (sch, i, got, ref[sch])
+
     dt = 0.1
     announce("largest grid, linear FS", N, prec, "F =", 1 + p)
-    s.set_fields(u)
     s.step_fs(dt, steps)
     torch.cuda.synchronize()
     k2 = _symbol(lambda m, n, h: (2 * np.pi * m / (n * h)) ** 2, torch, dev)

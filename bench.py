@@ -114,6 +114,41 @@ def pass_rates(solver, cfg, prec, reps):
     return out
 
 
+def energy_passes(solver, cfg, prec, reps=20):
+    """Device time per launch of the kernels of one pf_energy call (HIP events
+    around each launch, pf_profile_*), for both gradient forms, with the rate
+    on each kernel's compulsory bytes.  Spectral form: the row pass reads the
+    F real fields and writes their F x-spectra, the column pass reads those
+    (its outputs are per-work-group partial sums).  FD form: one kernel
+    reading the F real fields.  Each call ends in a host readback, so every
+    pass starts on an idle GPU."""
+    from paper_2306_04322_amd import pfspec as PF
+    F = 1 + cfg["p"]
+    nx, ny = cfg["n"][0], cfg["n"][1]
+    nz = cfg["n"][2] if cfg["ndim"] == 3 else 1
+    s = 4 if prec == "f32" else 8
+    real = F * nx * ny * nz * s
+    spec = F * (nx // 2 + 1) * ny * nz * 2 * s
+    out = {}
+    for scheme, kernels in (("fs", (("row", PF.PROF_ROW, real + spec), ("col", PF.PROF_COL, spec))),
+                            ("fd", (("fd", PF.PROF_FD, real),))):
+        PF.pf_profile_enable(solver.h, True)
+        for _ in range(reps):
+            solver.energy(scheme)
+        rec = {}
+        for name, cls, nb in kernels + (("reduce", PF.PROF_RED, 0),):
+            n, ms = PF.pf_profile_read(solver.h, cls)
+            us = 1e3 * ms / max(1, n)
+            rec[name] = {"launches": n, "avg_launch_us": round(us, 2)}
+            if nb:
+                rec[name].update({"compulsory_bytes_per_launch": nb,
+                                  "compulsory_GBs": round(nb / (us * 1e-6) / 1e9, 1),
+                                  "frac": round(nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)})
+        PF.pf_profile_enable(solver.h, False)
+        out[scheme] = rec
+    return out
+
+
 def passes_3d(solver, prec, dt, steps=10):
     """Per-pass times of the 3D 256^3 FS step and the rates on each pass's
     compulsory bytes (F = 5 x-spectra in and out; the z update one more each
@@ -440,6 +475,7 @@ def main(argv=None):
         for _ in range(20):
             sfd.energy("fs")
         extras["energy_2d_1024_f32_ms"] = 1e3 * (time.perf_counter() - t0) / 20
+        extras["energy_2d_1024_f32_passes"] = energy_passes(sfd, cfg, "f32")
         del sfd
         torch.cuda.empty_cache()
         # 3D 256^3, c + 4 eta

@@ -517,23 +517,36 @@ __global__ void __launch_bounds__(256) fd_energy_kernel(FdArgs<T> a) {
   if (i < a.P) {
     const Nb n = neighbours(a, i);
     const int p = a.F - 1;
+    // every value first, all loads in flight together: slots beyond F read
+    // field 0 again and are not used (in 2D the z neighbour is the point)
+    constexpr int FM = PMAX + 1;
+    T vc[FM], vx[FM], vy[FM], vz[FM];
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+      const T* v = a.in + (long long)(f < a.F ? f : 0) * a.P;
+      vc[f] = v[i];
+      vx[f] = v[n.xp];
+      vy[f] = v[n.yp];
+      vz[f] = v[n.zp];
+    }
     T eta[PMAX];
 #pragma unroll
-    for (int j = 0; j < PMAX; ++j) eta[j] = (j < p) ? a.in[(j + 1) * a.P + i] : T(0);
-    const T c = a.in[i];
-    acc[0] = fe_density<T, PMAX>(a.fe, p, c, eta);
-    acc[3] = double(c);
-    for (int f = 0; f < a.F; ++f) {
-      const T* v = a.in + f * a.P;
-      const double vc = double(v[i]);
-      double dx = (double(v[n.xp]) - vc) * a.ix;
-      double dy = (double(v[n.yp]) - vc) * a.iy;
-      double s = dx * dx + dy * dy;
-      if (a.ndim == 3) {
-        const double dz = (double(v[n.zp]) - vc) * a.iz;
-        s += dz * dz;
+    for (int j = 0; j < PMAX; ++j) eta[j] = (j < p) ? vc[j + 1] : T(0);
+    acc[0] = fe_density<T, PMAX>(a.fe, p, vc[0], eta);
+    acc[3] = double(vc[0]);
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+      if (f < a.F) {
+        const double c = double(vc[f]);
+        double dx = (double(vx[f]) - c) * a.ix;
+        double dy = (double(vy[f]) - c) * a.iy;
+        double s = dx * dx + dy * dy;
+        if (a.ndim == 3) {
+          const double dz = (double(vz[f]) - c) * a.iz;
+          s += dz * dz;
+        }
+        acc[f == 0 ? 1 : 2] += s;
       }
-      acc[f == 0 ? 1 : 2] += s;
     }
   }
   block_sum<4>(acc, red);

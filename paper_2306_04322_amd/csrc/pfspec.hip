@@ -269,8 +269,9 @@ pf_status reduce(pf_handle* h, int n, int width, double* out, double s0, double 
                  double s3, int accumulate = 0) {
   const double sc[4] = {s0, s1, s2, s3};
   const int pi = prof_begin(h, PROF_RED);
-  reduce_launch(partials(h), n, width, out, sc, accumulate, h->stream);
+  const int g = reduce_launch(partials(h), n, width, out, sc, accumulate, h->stream);
   prof_end(h, pi);
+  if (g < 0) return fail(PF_ERR_UNSUPPORTED, "reduction: record width must be 2 or 4");
   return check_launch("reduction");
 }
 

@@ -508,44 +508,54 @@ __global__ void __launch_bounds__(FD_ZL_WG) fd_c_zl_kernel(FdArgs<T> a, int zb) 
 }
 
 // partials[block] = {sum f(u), sum_d (dc/dx_d)^2, sum_i sum_d (deta_i/dx_d)^2, sum c}
-// with forward differences, accumulated in double.
-template <typename T, int PMAX>
+// with forward differences, accumulated in double.  Each thread takes the V
+// consecutive x points of one vector and adds them in increasing x.  Every
+// value is loaded before any is used, so all loads are in flight together.
+// Slots beyond F read field 0 again and are not used; in 2D the z neighbour
+// vector is the centre one.
+template <typename T, int PMAX, int V>
 __global__ void __launch_bounds__(256) fd_energy_kernel(FdArgs<T> a) {
   __shared__ double red[4 * 4];
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long i0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * V;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (i < a.P) {
-    const Nb n = neighbours(a, i);
+  if (i0 < a.P) {
+    const NbV n = neighbours_vec<T, V>(a, i0);
     const int p = a.F - 1;
-    // every value first, all loads in flight together: slots beyond F read
-    // field 0 again and are not used (in 2D the z neighbour is the point)
     constexpr int FM = PMAX + 1;
-    T vc[FM], vx[FM], vy[FM], vz[FM];
+    FdVec<T, V> vc[FM], vy[FM], vz[FM];
+    T vr[FM];
 #pragma unroll
     for (int f = 0; f < FM; ++f) {
       const T* v = a.in + (long long)(f < a.F ? f : 0) * a.P;
-      vc[f] = v[i];
-      vx[f] = v[n.xp];
-      vy[f] = v[n.yp];
-      vz[f] = v[n.zp];
+      vc[f] = ld_vec<T, V>(v + i0);
+      vy[f] = ld_vec<T, V>(v + n.yp);
+      vz[f] = ld_vec<T, V>(v + n.zp);
+      vr[f] = v[n.xr];
     }
-    T eta[PMAX];
 #pragma unroll
-    for (int j = 0; j < PMAX; ++j) eta[j] = (j < p) ? vc[j + 1] : T(0);
-    acc[0] = fe_density<T, PMAX>(a.fe, p, vc[0], eta);
-    acc[3] = double(vc[0]);
+    for (int k = 0; k < V; ++k) {
+      T eta[PMAX];
+#pragma unroll
+      for (int j = 0; j < PMAX; ++j) eta[j] = (j < p) ? vc[j + 1].v[k] : T(0);
+      acc[0] += fe_density<T, PMAX>(a.fe, p, vc[0].v[k], eta);
+      acc[3] += double(vc[0].v[k]);
+    }
 #pragma unroll
     for (int f = 0; f < FM; ++f) {
       if (f < a.F) {
-        const double c = double(vc[f]);
-        double dx = (double(vx[f]) - c) * a.ix;
-        double dy = (double(vy[f]) - c) * a.iy;
-        double s = dx * dx + dy * dy;
-        if (a.ndim == 3) {
-          const double dz = (double(vz[f]) - c) * a.iz;
-          s += dz * dz;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          const double c = double(vc[f].v[k]);
+          const double right = double(k == V - 1 ? vr[f] : vc[f].v[k + 1]);
+          const double dx = (right - c) * a.ix;
+          const double dy = (double(vy[f].v[k]) - c) * a.iy;
+          double s = dx * dx + dy * dy;
+          if (a.ndim == 3) {
+            const double dz = (double(vz[f].v[k]) - c) * a.iz;
+            s += dz * dz;
+          }
+          acc[f == 0 ? 1 : 2] += s;
         }
-        acc[f == 0 ? 1 : 2] += s;
       }
     }
   }
@@ -637,8 +647,19 @@ static int fd_go(int which, const FdArgs<T>& a, hipStream_t s) {
     if (v == 2) return fd_go_v<T, PMAX, 2>(which, a, s);
     return fd_go_v<T, PMAX, 1>(which, a, s);
   }
-  const int grid = int((a.P + 255) / 256);
-  hipLaunchKernelGGL((fd_energy_kernel<T, PMAX>), dim3(grid), dim3(256), 0, s, a);
+  // the energy pass: vectors as wide as the step kernels use
+  const int v = fd_vec_width<T>(a.P);
+  const int grid = int((a.P / v + 255) / 256);
+  if constexpr (sizeof(T) == 4) {
+    if (v == 4) {
+      hipLaunchKernelGGL((fd_energy_kernel<T, PMAX, 4>), dim3(grid), dim3(256), 0, s, a);
+      return grid;
+    }
+  }
+  if (v == 2)
+    hipLaunchKernelGGL((fd_energy_kernel<T, PMAX, 2>), dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((fd_energy_kernel<T, PMAX, 1>), dim3(grid), dim3(256), 0, s, a);
   return grid;
 }
 

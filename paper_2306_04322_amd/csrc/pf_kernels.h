@@ -28,7 +28,8 @@
 // Column pass (col_kernel): transforms along a strided axis (y, or z in
 // 3D) for a tile of C consecutive x-spectrum columns.  Lanes are laid out
 // column-fastest so every global access of a wavefront covers contiguous
-// 128-byte row segments.  Modes: forward only, inverse only, the k-space
+// row segments of C values (128 bytes on axes shorter than 512 points, 16
+// or 32 bytes on the longer ones, where tiles are narrower).  Modes: forward only, inverse only, the k-space
 // update of Eq. (12)-(15) between a forward and an inverse transform, the
 // adjoint multipliers, and the spectral gradient-energy sums.
 #pragma once
@@ -938,11 +939,12 @@ struct ColArgs {
   double invPd;  // 1 / P in double
 };
 
-// Column-pass geometry.  E = 8 elements per lane (N / 8 lanes per column),
+// Column-pass geometry.  E elements per lane (8; N when N <= 8; for float
+// axes of 512 points or more, PF_COL_E_LONG_F32), N / E lanes per column,
 // C consecutive columns per work-group: a few columns on the long axes
 // (N >= 512) so that a 2D grid yields several work-groups per compute unit,
 // 128-byte row segments otherwise; at least one wavefront and at most 512
-// lanes per group.
+// lanes per group (PF_COL_WG_MAX_LONG for 4096-point float axes).
 template <typename T, int N>
 struct ColGeom {
   static constexpr int E = N <= 8 ? N : ((N >= 512 && sizeof(T) == 4) ? PF_COL_E_LONG_F32 : 8);
